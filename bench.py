@@ -1,0 +1,231 @@
+"""Benchmark of the spectral-element Poisson hot path on one MI355X.
+
+Step = one Jacobi-PCG solve to ||r||_c <= 1e-8 ||b||_c from x = 0 on the
+32x32x32 deformed hex mesh at N = 7 (E = 32768, 16.8 M element-local nodes),
+with the operator already set up and the right-hand side resident in HBM.
+Throughput is the paper's GDOFS measure (Sec. VIII-B, Eq. gdofs):
+E*N^3*iterations / time / 1e9.
+
+Beside it the bench times the A.u operator kernel alone (the roofline study of
+the same mesh) with HIP events on the stream it runs on, and the FP64 CPU
+oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
+METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latency"
+
+
+def _kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sem_ax.hip", "sem_internal.h"):
+        with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel_hash: str):
+    """HBM bytes per launch of the A.u kernel from committed rocprofv3 counter
+    runs, if they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "ax_f64_n7_e32768_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds_target: float = 15.0):
+    """The FP64 NumPy oracle's Jacobi-PCG on a bounded sample of the workload:
+    a 12x12x12 block of the same deformed N = 7 mesh family, timed per
+    iteration and scaled to GDOF/s (setup excluded, as on the GPU)."""
+    import numpy as np
+
+    import workload
+    from oracle import operator as op
+    from oracle import pcg as opcg
+
+    nx = ny = nz = 12
+    N, amp = 7, 0.05
+    pr = op.Problem(nx, ny, nz, N, amp)
+    b = pr.shape4(workload.continuous_rhs(4, nx, ny, nz, N))
+    # one short run to size the sample to about `seconds_target`
+    t0 = time.perf_counter()
+    opcg.pcg(pr.ax, b, pr.minv, pr.c, fixed_iter=2)
+    per_it = (time.perf_counter() - t0) / 2
+    iters = max(3, min(200, int(seconds_target / max(per_it, 1e-6))))
+    t0 = time.perf_counter()
+    opcg.pcg(pr.ax, b, pr.minv, pr.c, fixed_iter=iters)
+    dt = time.perf_counter() - t0
+    gdofs = pr.E * N ** 3 * iters / dt / 1e9
+    return {
+        "value": gdofs,
+        "unit": "GDOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"oracle FP64 Jacobi-PCG, {iters} iterations on the 12x12x12 deformed N=7 mesh "
+                  f"(E=1728, same element shape as the timed 32^3 mesh), {dt:.1f} s; single-threaded "
+                  f"NumPy (host nproc={os.cpu_count()})",
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ax-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path is single-GPU; see the sharding notes in the design document)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    nx = ny = nz = 32
+    N, amp, rtol = 7, 0.05, 1e-8
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        A = sem.SemOperator(nx, ny, nz, N, amp, device=dev)
+        b = torch.from_numpy(workload.continuous_rhs(4, nx, ny, nz, N)).to(dev)
+        x = torch.empty_like(b)
+        w = torch.empty_like(b)
+        torch.cuda.synchronize()
+        print(f"[bench] setup done: E={A.E} N={N} L={A.L}", file=sys.stderr, flush=True)
+
+        # ---- warm-up and timed solves
+        iters = []
+        for _ in range(args.warmup):
+            _, res = A.cg(b, x, rtol=rtol)
+            iters.append(res.iters)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        timed_iters = 0
+        res = None
+        for _ in range(args.steps):
+            _, res = A.cg(b, x, rtol=rtol)
+            timed_iters += res.iters
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        wall = t1 - t0
+        ev_ms = ev0.elapsed_time(ev1)
+        if res is None or res.status != 0:
+            print(f"[bench] solve failed: {res}", file=sys.stderr)
+            return 1
+        print(f"[bench] {args.steps} solves, {timed_iters} iterations, {wall:.3f} s", file=sys.stderr,
+              flush=True)
+
+        # ---- A.u operator kernel alone (sem_ax, element-local mode: one launch)
+        u = torch.from_numpy(workload.continuous_rhs(5, nx, ny, nz, N)).to(dev)
+        for _ in range(3):
+            A.ax(u, sem.LOCAL, out=w)
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(args.ax_reps):
+            A.ax(u, sem.LOCAL, out=w)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        ax_s = a0.elapsed_time(a1) / 1e3 / args.ax_reps
+        # masked A.u (operator + gather-scatter), the full sem_ax
+        m0 = torch.cuda.Event(enable_timing=True)
+        m1 = torch.cuda.Event(enable_timing=True)
+        m0.record(stream)
+        for _ in range(args.ax_reps):
+            A.ax(u, sem.MASKED, out=w)
+        m1.record(stream)
+        torch.cuda.synchronize()
+        axm_s = m0.elapsed_time(m1) / 1e3 / args.ax_reps
+
+    E, L = A.E, A.L
+    gdof = E * N ** 3
+    value = gdof * timed_iters / wall / 1e9
+    ax_bytes = 64.0 * L  # read u (1) + G (6), write w (1) doubles per node
+    achieved = ax_bytes / ax_s / 1e9
+    khash = _kernel_source_hash()
+    traffic = _traffic_from_profile(khash)
+    s_frac = 1.0 - ((N - 1) / (N + 1)) ** 3
+    cg_bytes_per_iter = (19 + 2 * s_frac) * 8.0 * L
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: continuous uniform[-1,1] RHS per global node (seed 4), homogeneous Dirichlet",
+        "config": {
+            "workload": "Jacobi-PCG to 1e-8 rel. residual, 32x32x32 hex box, N=7, "
+                        "deformed x+=0.05 sin(2pi x)sin(2pi y)sin(2pi z)",
+            "E": E, "N": N, "L": L, "gdof_per_iter": gdof, "rtol": rtol,
+        },
+        "solves_per_s": args.steps / wall,
+        "cg_iters_per_solve": timed_iters / args.steps,
+        "cg_event_ms_per_step": ev_ms / args.steps,
+        "cg_hbm_floor_frac": cg_bytes_per_iter * timed_iters / wall / 1e9 / HBM_PEAK_GBS,
+        "ax_local_us": ax_s * 1e6,
+        "ax_masked_us": axm_s * 1e6,
+        "ax_gdofs": gdof / ax_s / 1e9,
+        "ax_masked_gdofs": gdof / axm_s / 1e9,
+        "roofline": {
+            "kernel": "ax_f64_kernel<8,false> (sem_ax element operator, N=7)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": ax_bytes,
+            "avg_launch_us": ax_s * 1e6,
+            "kernel_source_hash": khash,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,164 @@
+/*
+ * sem.h - C ABI of the MI355X spectral-element Poisson library (libsem.so).
+ *
+ * The library applies the matrix-free high-order spectral-element Poisson
+ * operator of the Nekbone workload (paper Sec. VIII-A: a 3-D Poisson problem
+ * on a box of E hexahedra with (N+1)^3 Gauss-Lobatto-Legendre nodes each,
+ * solved by Jacobi-preconditioned CG; the operator is the "ax" kernel of
+ * Sec. VIII-B, the assembly is the "gs" gather-scatter of Sec. V-B) and runs
+ * that CG on one GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Return value: 0 (SEM_OK) or a negative SEM_ERR_* code.  Nothing throws or
+ *    aborts.  sem_last_error() returns a thread-local text for the last error.
+ *  - Arguments are validated before any launch; on SEM_ERR_ARG nothing was
+ *    enqueued.
+ *  - Pointers named *_dev are device pointers (HBM).  The library allocates
+ *    no device memory: every device buffer, including the workspace, belongs
+ *    to the caller and must stay alive while work that uses it is pending.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream unless stated otherwise.
+ *  - "L-vector": element-local storage of a nodal field, E*(N+1)^3 doubles,
+ *    index  e*(N+1)^3 + i + (N+1)*(j + (N+1)*k)  with i (the r direction)
+ *    fastest and  e = ex + nelx*(ey + nely*ez).  Node (i,j,k) of element
+ *    (ex,ey,ez) is the global lattice point (ex*N+i, ey*N+j, ez*N+k); nodes
+ *    on shared faces, edges and corners have one copy per element.
+ *  - The mesh is the box [0,1]^3 split into nelx*nely*nelz equal hexahedra;
+ *    deform_amp != 0 adds amp*sin(2 pi X)sin(2 pi Y)sin(2 pi Z) (at the
+ *    undeformed point X) to all three coordinates.  Homogeneous Dirichlet
+ *    conditions hold on every box face.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sem_status {
+  SEM_OK = 0,
+  SEM_ERR_ARG = -1,         /* invalid argument (null pointer, size, order)  */
+  SEM_ERR_HIP = -2,         /* a HIP runtime call failed; text in last_error  */
+  SEM_ERR_NOMEM = -3,       /* caller workspace smaller than required         */
+  SEM_ERR_NOTCONV = -4,     /* CG hit its iteration cap before the tolerance  */
+  SEM_ERR_BREAKDOWN = -5,   /* CG found p^T A p <= 0 or a non-finite scalar   */
+  SEM_ERR_UNSUPPORTED = -6  /* order or precision outside the compiled set    */
+};
+
+/* Arithmetic of the optional low-precision operator copy. */
+enum sem_prec { SEM_F64 = 0, SEM_F32 = 1, SEM_BF16 = 2 };
+
+/* What sem_ax returns (the Poisson operator of Sec. VIII-B with or without
+ * the gather-scatter of Sec. V-B):
+ *   SEM_AX_LOCAL     w = A_L u           element-by-element operator only
+ *   SEM_AX_ASSEMBLED w = Q Q^T A_L u     copies of a shared node summed
+ *   SEM_AX_MASKED    w = mask o Q Q^T A_L u   (the A of the CG)             */
+enum sem_ax_mode { SEM_AX_LOCAL = 0, SEM_AX_ASSEMBLED = 1, SEM_AX_MASKED = 3 };
+
+/* Fields sem_export can copy out (setup results, for inspection). */
+enum sem_field {
+  SEM_FIELD_G = 0,     /* geometric factors, E x 6 x (N+1)^3 doubles, per element
+                          the planes rr, rs, rt, ss, st, tt;
+                          G = w_i w_j w_k det(J) J^-1 J^-T at each node          */
+  SEM_FIELD_MINV = 1,  /* Jacobi inverse diagonal, L doubles (0 on the boundary) */
+  SEM_FIELD_D = 2,     /* 1-D derivative matrix, (N+1)^2 doubles, D[a*(N+1)+b] =
+                          l_b'(xi_a)                                            */
+  SEM_FIELD_NODES = 3, /* GLL nodes xi_0..xi_N then weights w_0..w_N            */
+  SEM_FIELD_C = 4      /* inverse multiplicity 1/mult, L doubles                */
+};
+
+typedef struct sem_ctx sem_ctx;  /* opaque host-side handle */
+
+typedef struct {
+  int32_t nelx, nely, nelz; /* elements per direction, each >= 1               */
+  int32_t order;            /* polynomial order N, 1..12                        */
+  double deform_amp;        /* 0 = affine elements                              */
+  int32_t lowprec;          /* SEM_F64 (none), SEM_F32 or SEM_BF16: also keep a
+                               rounded copy of G for the inner solver of the
+                               mixed-precision CG                              */
+  int32_t reserved;         /* must be 0                                        */
+} sem_mesh_desc;
+
+/* Device bytes sem_setup needs for this mesh (0 if the descriptor is invalid).
+ * It covers G, the Jacobi diagonal, D, the CG vectors and reduction scratch;
+ * it is the footprint a scheduler can admit a solve by. */
+size_t sem_workspace_bytes(const sem_mesh_desc *desc);
+
+/* Build the operator of `desc` in the caller's workspace: GLL nodes and D on
+ * the host, then on the GPU the mesh coordinates, the isoparametric metric G,
+ * the Jacobi diagonal (summed over copies) and its inverse.  `dev_ws` must be
+ * 256-byte aligned and hold sem_workspace_bytes(desc) bytes.  Synchronous:
+ * returns after the stream has finished the setup.  On success *out is a new
+ * handle (free with sem_destroy); the workspace belongs to it until then. */
+int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *stream,
+              sem_ctx **out);
+
+/* Free the host handle (and any captured CG graph).  Never frees dev_ws. */
+int sem_destroy(sem_ctx *ctx);
+
+/* L = E*(N+1)^3, or -1 for a null handle. */
+int64_t sem_nlocal(const sem_ctx *ctx);
+
+/* w = A u as selected by `mode` (enum sem_ax_mode), u and w L-vectors of
+ * doubles on the device, u != w.  u may be discontinuous for SEM_AX_LOCAL. */
+int sem_ax(sem_ctx *ctx, const double *u_dev, double *w_dev, int mode, void *stream);
+
+/* Options of sem_cg. */
+typedef struct {
+  double rtol;         /* stop when ||r||_c <= rtol*||b||_c (tolerance mode)    */
+  int32_t max_iter;    /* iteration cap in tolerance mode (<=0: 20000)          */
+  int32_t fixed_iter;  /* > 0: run exactly this many iterations, no tolerance   */
+  int32_t mixed;       /* 0: FP64 PCG.  1: inner-outer refinement with the
+                          low-precision operator copy (needs desc.lowprec)      */
+  int32_t check_every; /* iterations per captured graph replay (<=0: 25)        */
+  double inner_rtol;   /* mixed: inner relative tolerance (<=0: 1e-3)           */
+  int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 200)  */
+  int32_t reserved;
+} sem_cg_opts;
+
+typedef struct {
+  int32_t iters;        /* CG iterations (mixed: total inner iterations)       */
+  int32_t outer_iters;  /* mixed: outer refinement steps (else 0)              */
+  int32_t status;       /* SEM_OK, SEM_ERR_NOTCONV or SEM_ERR_BREAKDOWN        */
+  int32_t reserved;
+  double rel_res;       /* final ||r||_c/||b||_c (recursive; mixed: true FP64) */
+} sem_cg_info;
+
+/* Jacobi-PCG for A x = b (Sec. VIII-A) with x_0 = 0, c-weighted dots
+ * <x,y>_c = sum_i x_i y_i / mult_i, scalars kept on the device.  b and x are
+ * L-vectors (b continuous; boundary entries are ignored), x is overwritten.
+ * Blocking: returns when the solve has finished; polls one small status word
+ * every check_every iterations.  The return value equals info->status. */
+int sem_cg(sem_ctx *ctx, const double *b_dev, double *x_dev, const sem_cg_opts *opts,
+           sem_cg_info *info, void *stream);
+
+/* y <- alpha*x + y over n doubles (a streaming update of CG, Sec. VIII-B).
+ * n >= 0; x and y device pointers (may be null only when n == 0). */
+int vec_axpy(int64_t n, double alpha, const double *x_dev, double *y_dev, void *stream);
+
+/* Device scratch vec_dot needs for length n. */
+size_t vec_dot_workspace_bytes(int64_t n);
+
+/* *out_dev <- sum_i wt_i x_i y_i (wt_dev may be NULL: weight 1), a two-stage
+ * tree reduction (Sec. VIII-B) in a fixed order: the result depends only on n
+ * and the data, so repeated calls are bitwise identical.  out_dev is one
+ * device double; dev_ws holds vec_dot_workspace_bytes(n) bytes. */
+int vec_dot(int64_t n, const double *x_dev, const double *y_dev, const double *wt_dev,
+            double *out_dev, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* Copy a setup field (enum sem_field) into dst_dev, which must hold the size
+ * listed with the field. */
+int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);
+
+/* Thread-local text of the last error ("" if none). */
+const char *sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

@@ -156,3 +156,52 @@ class Problem:
 
     def dssum(self, v):
         return self._dss(self.shape4(v), self.gid)
+
+
+class Patch:
+    """An element and its (up to 26) neighbours in a large box mesh.
+
+    Every copy of a node of the centre element lies in the patch, so the
+    assembled, masked operator at the centre element's nodes can be evaluated
+    from the patch alone: this is how large meshes are checked at sampled
+    elements without building the whole mesh.
+    """
+
+    def __init__(self, nx, ny, nz, N, amp, center):
+        from .mesh import box_coords, dirichlet_mask, element_coords, global_ids
+        self.N, self.n = N, N + 1
+        ex, ey, ez = element_coords(center, nx, ny)
+        elems = []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    a, b, c = ex + dx, ey + dy, ez + dz
+                    if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz:
+                        elems.append(a + nx * (b + ny * c))
+        self.elements = sorted(elems)
+        self.center_slot = self.elements.index(center)
+        self.xi, self.w = gll_nodes_weights(N)
+        self.D = deriv_matrix(N, self.xi)
+        X, Y, Z = box_coords(nx, ny, nz, N, amp, self.xi, self.elements)
+        self.G, self.detJ = geometric_factors(X, Y, Z, self.D, self.w)
+        self.gid = global_ids(nx, ny, nz, N, self.elements)
+        n3 = self.n ** 3
+        self.mask_center = dirichlet_mask(nx, ny, nz, N, [center]).reshape(self.n, self.n, self.n)
+        self.center_gid = self.gid[self.center_slot * n3:(self.center_slot + 1) * n3]
+
+    def ax_center(self, u_patch, mode="masked"):
+        """A_L, dssum(A_L) or mask o dssum(A_L) of u_patch at the centre
+        element's nodes; u_patch has the patch elements' L entries in order."""
+        n = self.n
+        wl = ax_local(np.asarray(u_patch, dtype=np.float64).reshape(-1, n, n, n), self.D, self.G)
+        if mode == "local":
+            return wl[self.center_slot]
+        flat = wl.reshape(-1)
+        sums = {}
+        for idx in np.argsort(self.gid, kind="stable"):
+            g = int(self.gid[idx])
+            sums[g] = sums.get(g, 0.0) + flat[idx]
+        out = np.array([sums[int(g)] for g in self.center_gid]).reshape(n, n, n)
+        if mode == "masked":
+            out = out * self.mask_center
+        return out

@@ -1,0 +1,430 @@
+// C-ABI entry points of libsem (declared in include/sem.h): argument checks,
+// workspace layout, host-side basis construction and the device-resident CG
+// driver (Jacobi PCG of paper Sec. VIII-A, iterations captured in a HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sem_internal.h"
+
+using semk::Box;
+using semk::CgState;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return SEM_ERR_HIP;
+}
+
+#define SEM_HIP(call)                                     \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Byte offsets of every buffer inside the caller's workspace.
+struct Layout {
+  size_t D, nodes, G, minv, r, p, w, part_ax, part_rr, part_rz, state, total;
+};
+
+bool desc_valid(const sem_mesh_desc *d, std::string *why) {
+  if (!d) { *why = "null mesh descriptor"; return false; }
+  if (d->nelx < 1 || d->nely < 1 || d->nelz < 1) { *why = "element counts must be >= 1"; return false; }
+  if (d->order < semk::kMinOrder || d->order > semk::kMaxOrder) {
+    *why = "order N must be in [1, 12]";
+    return false;
+  }
+  if (d->lowprec != SEM_F64 && d->lowprec != SEM_F32 && d->lowprec != SEM_BF16) {
+    *why = "lowprec must be SEM_F64, SEM_F32 or SEM_BF16";
+    return false;
+  }
+  if (d->reserved != 0) { *why = "reserved field must be 0"; return false; }
+  if (!std::isfinite(d->deform_amp)) { *why = "deform_amp must be finite"; return false; }
+  const double L = (double)d->nelx * d->nely * d->nelz * std::pow(d->order + 1.0, 3);
+  if (L > 4.0e9) { *why = "mesh too large (L > 4e9)"; return false; }
+  return true;
+}
+
+Box box_of(const sem_mesh_desc *d) { return Box{d->nelx, d->nely, d->nelz, d->order}; }
+
+Layout layout_of(const sem_mesh_desc *d) {
+  const Box b = box_of(d);
+  const size_t L = (size_t)b.L();
+  const size_t n1 = (size_t)b.n1();
+  Layout o;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t off = at;
+    at = align_up(at + bytes);
+    return off;
+  };
+  o.D = take(n1 * n1 * sizeof(double));
+  o.nodes = take(2 * n1 * sizeof(double));
+  o.G = take(6 * L * sizeof(double));
+  o.minv = take(L * sizeof(double));
+  o.r = take(L * sizeof(double));
+  o.p = take(L * sizeof(double));
+  o.w = take(L * sizeof(double));
+  o.part_ax = take((size_t)semk::ax_num_blocks(b) * sizeof(double));
+  o.part_rr = take((size_t)semk::vec_num_blocks(b.L()) * sizeof(double));
+  o.part_rz = take((size_t)semk::vec_num_blocks(b.L()) * sizeof(double));
+  o.state = take(sizeof(CgState));
+  o.total = at;
+  return o;
+}
+
+// ---------------------------------------------------------------- GLL basis
+// Legendre P_N and P_N' at x by the three-term recurrence, in long double.
+void legendre_pd(int N, long double x, long double *p, long double *dp) {
+  long double p0 = 1.0L, p1 = x, d0 = 0.0L, d1 = 1.0L;
+  if (N == 0) { *p = 1.0L; *dp = 0.0L; return; }
+  for (int n = 1; n < N; ++n) {
+    const long double p2 = ((2 * n + 1) * x * p1 - n * p0) / (n + 1);
+    const long double d2 = d0 + (2 * n + 1) * p1;  // P'_{n+1} = P'_{n-1} + (2n+1) P_n
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  *p = p1;
+  *dp = d1;
+}
+
+// GLL nodes (ascending) and weights.  Interior nodes: Newton on P_N' with
+// P_N'' from Legendre's equation (1-x^2) P'' = 2x P' - N(N+1) P, started at
+// the Chebyshev-Lobatto points; weights 2/(N(N+1) P_N(x)^2).
+void gll_host(int N, std::vector<double> *xs, std::vector<double> *ws) {
+  std::vector<long double> x(N + 1);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i <= N; ++i) x[i] = -cosl(pi * i / N);
+  for (int i = 1; i < N; ++i) {
+    long double v = x[i];
+    for (int it = 0; it < 60; ++it) {
+      long double p, dp;
+      legendre_pd(N, v, &p, &dp);
+      const long double d2 = (2.0L * v * dp - N * (N + 1.0L) * p) / (1.0L - v * v);
+      const long double dv = dp / d2;
+      v -= dv;
+      if (fabsl(dv) < 1e-19L) break;
+    }
+    x[i] = v;
+  }
+  x[0] = -1.0L;
+  x[N] = 1.0L;
+  xs->assign(N + 1, 0.0);
+  ws->assign(N + 1, 0.0);
+  for (int i = 0; i <= N; ++i) {
+    // symmetric node set: average the two mirrored estimates
+    const long double v = 0.5L * (x[i] - x[N - i]);
+    long double p, dp;
+    legendre_pd(N, v, &p, &dp);
+    (*xs)[i] = (double)v;
+    (*ws)[i] = (double)(2.0L / (N * (N + 1.0L) * p * p));
+  }
+  if (N % 2 == 0) (*xs)[N / 2] = 0.0;
+}
+
+// D[a][b] = l_b'(x_a) = P_N(x_a) / (P_N(x_b) (x_a - x_b)) off the diagonal;
+// -N(N+1)/4 and N(N+1)/4 at the two ends, 0 elsewhere on the diagonal.
+void deriv_host(int N, const std::vector<double> &xs, std::vector<double> *D) {
+  const int n1 = N + 1;
+  D->assign((size_t)n1 * n1, 0.0);
+  std::vector<long double> pn(n1);
+  for (int a = 0; a < n1; ++a) {
+    long double dp;
+    legendre_pd(N, (long double)xs[a], &pn[a], &dp);
+  }
+  for (int a = 0; a < n1; ++a)
+    for (int b = 0; b < n1; ++b)
+      if (a != b)
+        (*D)[a * n1 + b] = (double)(pn[a] / (pn[b] * ((long double)xs[a] - (long double)xs[b])));
+  (*D)[0] = -N * (N + 1) / 4.0;
+  (*D)[(size_t)N * n1 + N] = N * (N + 1) / 4.0;
+}
+
+}  // namespace
+
+struct sem_ctx {
+  sem_mesh_desc desc;
+  Box box;
+  semk::Skeleton sk;
+  Layout lay;
+  char *ws;
+  size_t ws_bytes;
+  double *D, *nodes, *G, *minv, *r, *p, *w, *part_ax, *part_rr, *part_rz;
+  CgState *st;
+  int64_t n_ax_blocks, n_vec_blocks;
+  CgState host_state;  // staging for the state upload / status reads
+  // cached graph of `graph_iters` CG iterations writing into graph_x
+  hipGraphExec_t graph;
+  hipStream_t graph_stream;
+  double *graph_x;
+  int graph_iters;
+};
+
+namespace {
+
+int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
+  const Box &b = c->box;
+  SEM_HIP(semk::launch_ax_f64(b, c->D, c->G, c->p, c->w, c->r, c->minv, c->st, c->part_ax, s));
+  SEM_HIP(semk::launch_dssum(b, c->sk, c->w, 1, &c->st->done, s));
+  SEM_HIP(semk::launch_cg_finalize_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
+  SEM_HIP(semk::launch_cg_update(b, x, c->p, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_finalize_beta(c->st, c->part_rr, c->part_rz, c->n_vec_blocks, s));
+  return SEM_OK;
+}
+
+void drop_graph(sem_ctx *c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_stream = nullptr;
+  c->graph_x = nullptr;
+  c->graph_iters = 0;
+}
+
+// Capture `iters` CG iterations on stream s into c->graph.  Returns SEM_OK, or
+// a positive value when capture is not possible (the caller then launches
+// directly), or a negative error.
+int capture_graph(sem_ctx *c, double *x, int iters, hipStream_t s) {
+  if (c->graph && c->graph_stream == s && c->graph_x == x && c->graph_iters == iters) return SEM_OK;
+  drop_graph(c);
+  if (s == nullptr) return 1;  // the legacy null stream cannot be captured
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  int rc = SEM_OK;
+  for (int it = 0; it < iters && rc == SEM_OK; ++it) rc = enqueue_cg_iteration(c, x, s);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != SEM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  c->graph = ex;
+  c->graph_stream = s;
+  c->graph_x = x;
+  c->graph_iters = iters;
+  return SEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sem_last_error(void) { return g_last_error.c_str(); }
+
+size_t sem_workspace_bytes(const sem_mesh_desc *desc) {
+  std::string why;
+  if (!desc_valid(desc, &why)) return 0;
+  return layout_of(desc).total;
+}
+
+int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *stream,
+              sem_ctx **out) {
+  std::string why;
+  if (!out) return fail(SEM_ERR_ARG, "sem_setup: null output handle");
+  *out = nullptr;
+  if (!desc_valid(desc, &why)) return fail(SEM_ERR_ARG, "sem_setup: " + why);
+  if (!dev_ws) return fail(SEM_ERR_ARG, "sem_setup: null workspace");
+  if (((uintptr_t)dev_ws) % kAlign != 0) return fail(SEM_ERR_ARG, "sem_setup: workspace not 256-byte aligned");
+  const Layout lay = layout_of(desc);
+  if (ws_bytes < lay.total)
+    return fail(SEM_ERR_NOMEM, "sem_setup: workspace has " + std::to_string(ws_bytes) +
+                                   " bytes, needs " + std::to_string(lay.total));
+  hipStream_t s = (hipStream_t)stream;
+  sem_ctx *c = new sem_ctx();
+  c->desc = *desc;
+  c->box = box_of(desc);
+  c->sk = semk::make_skeleton(c->box);
+  c->lay = lay;
+  c->ws = (char *)dev_ws;
+  c->ws_bytes = ws_bytes;
+  c->D = (double *)(c->ws + lay.D);
+  c->nodes = (double *)(c->ws + lay.nodes);
+  c->G = (double *)(c->ws + lay.G);
+  c->minv = (double *)(c->ws + lay.minv);
+  c->r = (double *)(c->ws + lay.r);
+  c->p = (double *)(c->ws + lay.p);
+  c->w = (double *)(c->ws + lay.w);
+  c->part_ax = (double *)(c->ws + lay.part_ax);
+  c->part_rr = (double *)(c->ws + lay.part_rr);
+  c->part_rz = (double *)(c->ws + lay.part_rz);
+  c->st = (CgState *)(c->ws + lay.state);
+  c->n_ax_blocks = semk::ax_num_blocks(c->box);
+  c->n_vec_blocks = semk::vec_num_blocks(c->box.L());
+  c->graph = nullptr;
+
+  const int N = desc->order;
+  std::vector<double> xs, wq, D;
+  gll_host(N, &xs, &wq);
+  deriv_host(N, xs, &D);
+  std::vector<double> nodes(xs);
+  nodes.insert(nodes.end(), wq.begin(), wq.end());
+  auto bail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+  hipError_t e;
+  if ((e = hipMemcpyAsync(c->D, D.data(), D.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return bail(hip_fail(e, "sem_setup: upload D"));
+  if ((e = hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+    return bail(hip_fail(e, "sem_setup: upload nodes"));
+  if ((e = semk::launch_setup_geom(c->box, desc->deform_amp, c->D, c->nodes, c->G, c->minv, s)) != hipSuccess)
+    return bail(hip_fail(e, "sem_setup: geometry kernel"));
+  if ((e = semk::launch_dssum(c->box, c->sk, c->minv, 0, nullptr, s)) != hipSuccess)
+    return bail(hip_fail(e, "sem_setup: diagonal gather-scatter"));
+  if ((e = semk::launch_invert_diag(c->box, c->minv, s)) != hipSuccess)
+    return bail(hip_fail(e, "sem_setup: invert diagonal"));
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sem_setup: synchronize"));
+  *out = c;
+  return SEM_OK;
+}
+
+int sem_destroy(sem_ctx *ctx) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_destroy: null handle");
+  drop_graph(ctx);
+  delete ctx;
+  return SEM_OK;
+}
+
+int64_t sem_nlocal(const sem_ctx *ctx) { return ctx ? ctx->box.L() : -1; }
+
+int sem_ax(sem_ctx *ctx, const double *u, double *w, int mode, void *stream) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_ax: null handle");
+  if (!u || !w) return fail(SEM_ERR_ARG, "sem_ax: null vector");
+  if (u == w) return fail(SEM_ERR_ARG, "sem_ax: u and w must differ");
+  if (mode != SEM_AX_LOCAL && mode != SEM_AX_ASSEMBLED && mode != SEM_AX_MASKED)
+    return fail(SEM_ERR_ARG, "sem_ax: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
+  hipStream_t s = (hipStream_t)stream;
+  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
+                              nullptr, nullptr, nullptr, s));
+  if (mode != SEM_AX_LOCAL)
+    SEM_HIP(semk::launch_dssum(ctx->box, ctx->sk, w, mode == SEM_AX_MASKED ? 1 : 0, nullptr, s));
+  return SEM_OK;
+}
+
+int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, sem_cg_info *info,
+           void *stream) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_cg: null handle");
+  if (!b || !x || !opts || !info) return fail(SEM_ERR_ARG, "sem_cg: null argument");
+  if (b == x) return fail(SEM_ERR_ARG, "sem_cg: b and x must differ");
+  if (opts->mixed) return fail(SEM_ERR_UNSUPPORTED, "sem_cg: mixed precision is not available in this build");
+  if (opts->fixed_iter <= 0 && !(opts->rtol > 0.0))
+    return fail(SEM_ERR_ARG, "sem_cg: rtol must be > 0 unless fixed_iter > 0");
+  hipStream_t s = (hipStream_t)stream;
+  const int max_iter = opts->fixed_iter > 0 ? opts->fixed_iter : (opts->max_iter > 0 ? opts->max_iter : 20000);
+  int every = opts->check_every > 0 ? opts->check_every : 25;
+  if (every > max_iter) every = max_iter;
+
+  CgState &h = ctx->host_state;
+  std::memset(&h, 0, sizeof(h));
+  h.max_iter = max_iter;
+  h.rtol2 = opts->fixed_iter > 0 ? -1.0 : opts->rtol * opts->rtol;
+  SEM_HIP(hipMemcpyAsync(ctx->st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
+  SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->minv, ctx->part_rz,
+                               ctx->part_rr, s));
+  SEM_HIP(semk::launch_cg_finalize_init(ctx->st, ctx->part_rz, ctx->part_rr, ctx->n_vec_blocks, s));
+
+  int rc = capture_graph(ctx, x, every, s);
+  if (rc < 0) return rc;
+  const bool use_graph = (rc == SEM_OK);
+  int launched = 0;
+  for (;;) {
+    if (use_graph) {
+      SEM_HIP(hipGraphLaunch(ctx->graph, s));
+    } else {
+      for (int it = 0; it < every; ++it) {
+        rc = enqueue_cg_iteration(ctx, x, s);
+        if (rc != SEM_OK) return rc;
+      }
+    }
+    launched += every;
+    SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    if (h.done != semk::kRunning) break;
+    if (launched > max_iter + every) return fail(SEM_ERR_HIP, "sem_cg: device state stopped advancing");
+  }
+  info->iters = h.iter;
+  info->outer_iters = 0;
+  info->rel_res = h.bnorm2 > 0.0 ? std::sqrt(h.rnorm2 / h.bnorm2) : 0.0;
+  int status = SEM_OK;
+  if (h.done == semk::kBreakdown) status = SEM_ERR_BREAKDOWN;
+  else if (h.done == semk::kMaxIter && opts->fixed_iter <= 0) status = SEM_ERR_NOTCONV;
+  info->status = status;
+  if (status == SEM_ERR_BREAKDOWN) g_last_error = "sem_cg: breakdown (p^T A p <= 0 or non-finite)";
+  if (status == SEM_ERR_NOTCONV) g_last_error = "sem_cg: iteration cap reached";
+  return status;
+}
+
+int vec_axpy(int64_t n, double alpha, const double *x, double *y, void *stream) {
+  if (n < 0) return fail(SEM_ERR_ARG, "vec_axpy: n < 0");
+  if (n > 0 && (!x || !y)) return fail(SEM_ERR_ARG, "vec_axpy: null vector");
+  SEM_HIP(semk::launch_axpy(n, alpha, x, y, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+size_t vec_dot_workspace_bytes(int64_t n) {
+  if (n < 0) return 0;
+  const int64_t nb = semk::vec_num_blocks(n);
+  return (size_t)(nb > 0 ? nb : 1) * sizeof(double);
+}
+
+int vec_dot(int64_t n, const double *x, const double *y, const double *wt, double *out,
+            void *dev_ws, size_t ws_bytes, void *stream) {
+  if (n < 0) return fail(SEM_ERR_ARG, "vec_dot: n < 0");
+  if (n > 0 && (!x || !y)) return fail(SEM_ERR_ARG, "vec_dot: null vector");
+  if (!out) return fail(SEM_ERR_ARG, "vec_dot: null output");
+  if (!dev_ws) return fail(SEM_ERR_ARG, "vec_dot: null workspace");
+  if (((uintptr_t)dev_ws) % sizeof(double) != 0) return fail(SEM_ERR_ARG, "vec_dot: workspace not 8-byte aligned");
+  if (ws_bytes < vec_dot_workspace_bytes(n)) return fail(SEM_ERR_NOMEM, "vec_dot: workspace too small");
+  SEM_HIP(semk::launch_dot(n, x, y, wt, out, (double *)dev_ws, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+int sem_export(sem_ctx *ctx, int field, double *dst, void *stream) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_export: null handle");
+  if (!dst) return fail(SEM_ERR_ARG, "sem_export: null destination");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t L = (size_t)ctx->box.L();
+  const size_t n1 = (size_t)ctx->box.n1();
+  switch (field) {
+    case SEM_FIELD_G:
+      SEM_HIP(hipMemcpyAsync(dst, ctx->G, 6 * L * sizeof(double), hipMemcpyDeviceToDevice, s));
+      break;
+    case SEM_FIELD_MINV:
+      SEM_HIP(hipMemcpyAsync(dst, ctx->minv, L * sizeof(double), hipMemcpyDeviceToDevice, s));
+      break;
+    case SEM_FIELD_D:
+      SEM_HIP(hipMemcpyAsync(dst, ctx->D, n1 * n1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      break;
+    case SEM_FIELD_NODES:
+      SEM_HIP(hipMemcpyAsync(dst, ctx->nodes, 2 * n1 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      break;
+    case SEM_FIELD_C:
+      SEM_HIP(semk::launch_fill_c(ctx->box, dst, s));
+      break;
+    default:
+      return fail(SEM_ERR_ARG, "sem_export: unknown field");
+  }
+  return SEM_OK;
+}
+
+}  // extern "C"

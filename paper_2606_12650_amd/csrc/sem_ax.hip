@@ -1,0 +1,358 @@
+// Element kernels of the spectral-element Poisson operator on gfx950:
+// the metric setup and the FP64 operator w = A_L u (paper Sec. VIII-B, the
+// "ax" kernel, with N fixed at compile time as its jit clause does).
+//
+// Mapping (one element per (N+1)^2 threads): thread (i, j) of an element owns
+// the column of nodes (i, j, 0..N) in registers.  The contraction along t runs
+// in registers; the contractions along r and s read the element's tile from
+// LDS.  Every HBM access is a full-wave coalesced load or store of a k-plane
+// of the element (element-major layout, i fastest).
+#include <hip/hip_runtime.h>
+
+#include "sem_internal.h"
+
+namespace semk {
+namespace {
+
+template <int N1>
+struct AxCfg {
+  // elements per work-group: about 128 threads per group
+  static constexpr int EPB = (N1 * N1 >= 128) ? 1 : (128 / (N1 * N1));
+  static constexpr int THREADS = N1 * N1 * EPB;
+  static constexpr int P = N1 + 1;      // padded row (LDS bank spread)
+  static constexpr int PLANE = N1 * P;  // one k-plane of the padded tile
+  static constexpr int TILE = N1 * PLANE;
+  static constexpr int NP = N1 * N1 * N1;
+};
+
+constexpr int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Deterministic block sum through LDS (fixed pairing, any block size T).
+template <int T>
+__device__ double block_sum_lds(double v, double *sred) {
+  sred[threadIdx.x] = v;
+  __syncthreads();
+  constexpr int P2 = next_pow2(T);
+#pragma unroll
+  for (int s = P2 / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && (int)threadIdx.x + s < T) sred[threadIdx.x] += sred[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sred[0];
+}
+
+template <int N1, bool CG>
+__global__ void __launch_bounds__(AxCfg<N1>::THREADS)
+    ax_f64_kernel(int64_t E, const double *__restrict__ Dg, const double *__restrict__ G,
+                  double *u, double *__restrict__ w, const double *__restrict__ r,
+                  const double *__restrict__ minv, const CgState *__restrict__ st,
+                  double *__restrict__ part) {
+  using C = AxCfg<N1>;
+  constexpr int NP = C::NP;
+  constexpr int PL = N1 * N1;
+  __shared__ double sD[N1 * N1];
+  __shared__ double s1[C::EPB * C::TILE];
+  __shared__ double s2[C::EPB * C::TILE];
+
+  if (CG && st->done) return;  // uniform: converged solves skip all work
+
+  const int tid = threadIdx.x;
+  const int el = tid / PL;
+  const int ij = tid - el * PL;
+  const int i = ij % N1;
+  const int j = ij / N1;
+  const int64_t e = (int64_t)blockIdx.x * C::EPB + el;
+  const bool active = e < E;
+
+  for (int t = tid; t < N1 * N1; t += C::THREADS) sD[t] = Dg[t];
+
+  const int64_t base = e * NP + ij;
+  double uk[N1];
+  double g[6][N1];
+  if (active) {
+    if (CG) {
+      const double beta = st->beta;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) {
+        const int64_t idx = base + k * PL;
+        const double v = minv[idx] * r[idx] + beta * u[idx];
+        uk[k] = v;
+        u[idx] = v;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < N1; ++k) uk[k] = u[base + k * PL];
+    }
+    const double *Ge = G + e * 6 * NP + ij;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < N1; ++k) g[q][k] = Ge[q * NP + k * PL];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      uk[k] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) g[q][k] = 0.0;
+    }
+  }
+
+  double *S1 = s1 + el * C::TILE;
+  double *S2 = s2 + el * C::TILE;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) S1[k * C::PLANE + j * C::P + i] = uk[k];
+  __syncthreads();
+
+  double Da[N1], Db[N1];
+#pragma unroll
+  for (int l = 0; l < N1; ++l) {
+    Da[l] = sD[i * N1 + l];
+    Db[l] = sD[j * N1 + l];
+  }
+  double wr[N1], ws[N1], wt[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    double ur = 0.0, us = 0.0, ut = 0.0;
+#pragma unroll
+    for (int l = 0; l < N1; ++l) {
+      ur += Da[l] * S1[k * C::PLANE + j * C::P + l];
+      us += Db[l] * S1[k * C::PLANE + l * C::P + i];
+      ut += sD[k * N1 + l] * uk[l];
+    }
+    wr[k] = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
+    ws[k] = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
+    wt[k] = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    S1[k * C::PLANE + j * C::P + i] = wr[k];
+    S2[k * C::PLANE + j * C::P + i] = ws[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < N1; ++l) {
+    Da[l] = sD[l * N1 + i];
+    Db[l] = sD[l * N1 + j];
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int l = 0; l < N1; ++l) {
+      v += Da[l] * S1[k * C::PLANE + j * C::P + l];
+      v += Db[l] * S2[k * C::PLANE + l * C::P + i];
+      v += sD[l * N1 + k] * wt[l];
+    }
+    if (active) w[base + k * PL] = v;
+    acc += uk[k] * v;
+  }
+  if (CG) {
+    __syncthreads();  // s1 is reused as the reduction buffer
+    const double tot = block_sum_lds<C::THREADS>(acc, s1);
+    if (tid == 0) part[blockIdx.x] = tot;
+  }
+}
+
+// Metric setup: coordinates of the (deformed) box mesh, isoparametric
+// Jacobian by D along r, s, t, G = w_i w_j w_k det(J) J^-1 J^-T, then the
+// diagonal of the element operator.
+template <int N1>
+__global__ void __launch_bounds__(AxCfg<N1>::THREADS)
+    setup_geom_kernel(Box b, double amp, const double *__restrict__ Dg,
+                      const double *__restrict__ nodes, double *__restrict__ G,
+                      double *__restrict__ diag) {
+  using C = AxCfg<N1>;
+  constexpr int NP = C::NP;
+  constexpr int PL = N1 * N1;
+  constexpr int N = N1 - 1;
+  __shared__ double sD[N1 * N1];
+  __shared__ double sx[3][C::EPB * C::TILE];
+
+  const int tid = threadIdx.x;
+  const int el = tid / PL;
+  const int ij = tid - el * PL;
+  const int i = ij % N1;
+  const int j = ij / N1;
+  const int64_t e = (int64_t)blockIdx.x * C::EPB + el;
+  const bool active = e < b.E();
+  for (int t = tid; t < N1 * N1; t += C::THREADS) sD[t] = Dg[t];
+
+  const int64_t ee = active ? e : 0;
+  const int ex = (int)(ee % b.nx);
+  const int ey = (int)((ee / b.nx) % b.ny);
+  const int ez = (int)(ee / ((int64_t)b.nx * b.ny));
+  const double xi_i = nodes[i], xi_j = nodes[j];
+  const double X0 = (ex + 0.5 * (xi_i + 1.0)) / b.nx;
+  const double Y0 = (ey + 0.5 * (xi_j + 1.0)) / b.ny;
+  double *SX = sx[0] + el * C::TILE;
+  double *SY = sx[1] + el * C::TILE;
+  double *SZ = sx[2] + el * C::TILE;
+  const double twopi = 2.0 * M_PI;
+  for (int k = 0; k < N1; ++k) {
+    const double Z0 = (ez + 0.5 * (nodes[k] + 1.0)) / b.nz;
+    double bump = 0.0;
+    if (amp != 0.0) bump = amp * sin(twopi * X0) * sin(twopi * Y0) * sin(twopi * Z0);
+    const int o = k * C::PLANE + j * C::P + i;
+    SX[o] = X0 + bump;
+    SY[o] = Y0 + bump;
+    SZ[o] = Z0 + bump;
+  }
+  __syncthreads();
+
+  const double wij = nodes[N1 + i] * nodes[N1 + j];
+  const int64_t base = e * NP + ij;
+  double grr[N1], gss[N1], gtt[N1], grs[N1], grt[N1], gst[N1];
+  for (int k = 0; k < N1; ++k) {
+    double J[3][3];
+    double *S[3] = {SX, SY, SZ};
+    for (int d = 0; d < 3; ++d) {
+      double a = 0.0, bb = 0.0, c = 0.0;
+      for (int l = 0; l < N1; ++l) {
+        a += sD[i * N1 + l] * S[d][k * C::PLANE + j * C::P + l];
+        bb += sD[j * N1 + l] * S[d][k * C::PLANE + l * C::P + i];
+        c += sD[k * N1 + l] * S[d][l * C::PLANE + j * C::P + i];
+      }
+      J[d][0] = a;
+      J[d][1] = bb;
+      J[d][2] = c;
+    }
+    // cofactors; inv[m][d] = cof[d][m] / det
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double c10 = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    const double c11 = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    const double c12 = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    const double c20 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    const double c21 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    const double c22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    // rows of J^-1: R_m[d] = cof[d][m] / det
+    const double inv = 1.0 / det;
+    const double R0[3] = {c00 * inv, c10 * inv, c20 * inv};
+    const double R1[3] = {c01 * inv, c11 * inv, c21 * inv};
+    const double R2[3] = {c02 * inv, c12 * inv, c22 * inv};
+    const double sc = wij * nodes[N1 + k] * det;
+    grr[k] = sc * (R0[0] * R0[0] + R0[1] * R0[1] + R0[2] * R0[2]);
+    grs[k] = sc * (R0[0] * R1[0] + R0[1] * R1[1] + R0[2] * R1[2]);
+    grt[k] = sc * (R0[0] * R2[0] + R0[1] * R2[1] + R0[2] * R2[2]);
+    gss[k] = sc * (R1[0] * R1[0] + R1[1] * R1[1] + R1[2] * R1[2]);
+    gst[k] = sc * (R1[0] * R2[0] + R1[1] * R2[1] + R1[2] * R2[2]);
+    gtt[k] = sc * (R2[0] * R2[0] + R2[1] * R2[1] + R2[2] * R2[2]);
+    if (active) {
+      double *Ge = G + e * 6 * NP + ij + k * PL;
+      Ge[0 * NP] = grr[k];
+      Ge[1 * NP] = grs[k];
+      Ge[2 * NP] = grt[k];
+      Ge[3 * NP] = gss[k];
+      Ge[4 * NP] = gst[k];
+      Ge[5 * NP] = gtt[k];
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < N1; ++k) {
+    const int o = k * C::PLANE + j * C::P + i;
+    SX[o] = grr[k];
+    SY[o] = gss[k];
+    SZ[o] = gtt[k];
+  }
+  __syncthreads();
+  const double Dii = sD[i * N1 + i], Djj = sD[j * N1 + j];
+  for (int k = 0; k < N1; ++k) {
+    double d = 0.0;
+    for (int l = 0; l < N1; ++l) {
+      const double a = sD[l * N1 + i], bb = sD[l * N1 + j], c = sD[l * N1 + k];
+      d += a * a * SX[k * C::PLANE + j * C::P + l];
+      d += bb * bb * SY[k * C::PLANE + l * C::P + i];
+      d += c * c * SZ[l * C::PLANE + j * C::P + i];
+    }
+    const double Dkk = sD[k * N1 + k];
+    d += 2.0 * Dii * Djj * grs[k] + 2.0 * Dii * Dkk * grt[k] + 2.0 * Djj * Dkk * gst[k];
+    if (active) diag[base + k * PL] = d;
+  }
+  (void)N;
+}
+
+template <int N1>
+hipError_t ax_dispatch(const Box &b, const double *D, const double *G, double *u, double *w,
+                       const double *r, const double *minv, const CgState *cg, double *part,
+                       hipStream_t s) {
+  using C = AxCfg<N1>;
+  const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
+  if (blocks == 0) return hipSuccess;
+  if (cg)
+    hipLaunchKernelGGL((ax_f64_kernel<N1, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       b.E(), D, G, u, w, r, minv, cg, part);
+  else
+    hipLaunchKernelGGL((ax_f64_kernel<N1, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
+                       s, b.E(), D, G, u, w, r, minv, cg, part);
+  return hipGetLastError();
+}
+
+template <int N1>
+hipError_t setup_dispatch(const Box &b, double amp, const double *D, const double *nodes,
+                          double *G, double *diag, hipStream_t s) {
+  using C = AxCfg<N1>;
+  const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL((setup_geom_kernel<N1>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, b,
+                     amp, D, nodes, G, diag);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define SEM_FOR_EACH_ORDER(X) \
+  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+
+int ax_elements_per_block(int N) {
+  switch (N) {
+#define CASE(n) \
+  case n:       \
+    return AxCfg<n + 1>::EPB;
+    SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+    default:
+      return 1;
+  }
+}
+
+int64_t ax_num_blocks(const Box &b) {
+  const int epb = ax_elements_per_block(b.N);
+  return (b.E() + epb - 1) / epb;
+}
+
+hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
+                         const double *r, const double *minv, const CgState *cg, double *part,
+                         hipStream_t s) {
+  switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return ax_dispatch<n + 1>(b, D, G, u, w, r, minv, cg, part, s);
+    SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_setup_geom(const Box &b, double amp, const double *D, const double *nodes,
+                             double *G, double *diag, hipStream_t s) {
+  switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return setup_dispatch<n + 1>(b, amp, D, nodes, G, diag, s);
+    SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace semk

@@ -1,0 +1,61 @@
+"""The C-ABI library loads, exports every declared symbol and validates its
+arguments on the host (no GPU work is launched by these tests)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_12650_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sem.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) - {"sizeof"})
+
+
+def test_header_and_binding_agree():
+    assert _declared_functions() == sorted(L.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    lib = L.lib()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_host_only():
+    lib = L.lib()
+    d = L.SemMeshDesc(32, 32, 32, 7, 0.05, 0, 0)
+    nb = lib.sem_workspace_bytes(ctypes.byref(d))
+    Lpts = 32768 * 512
+    # G (6) + Minv + r + p + w = 10 doubles per point, plus small buffers
+    assert 80 * Lpts <= nb < 80 * Lpts + 4 * 2 ** 20
+    bad = L.SemMeshDesc(0, 1, 1, 7, 0.0, 0, 0)
+    assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
+    bad = L.SemMeshDesc(1, 1, 1, 13, 0.0, 0, 0)
+    assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_argument_errors_return_codes_without_launching():
+    lib = L.lib()
+    d = L.SemMeshDesc(2, 2, 2, 3, 0.0, 0, 0)
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: checks fail first
+    assert lib.sem_setup(None, fake, 1 << 30, None, ctypes.byref(ctx)) == L.SEM_ERR_ARG
+    assert lib.sem_setup(ctypes.byref(d), None, 1 << 30, None, ctypes.byref(ctx)) == L.SEM_ERR_ARG
+    assert lib.sem_setup(ctypes.byref(d), ctypes.c_void_p((1 << 20) + 8), 1 << 30, None,
+                         ctypes.byref(ctx)) == L.SEM_ERR_ARG
+    assert lib.sem_setup(ctypes.byref(d), fake, 16, None, ctypes.byref(ctx)) == L.SEM_ERR_NOMEM
+    assert b"needs" in lib.sem_last_error()
+    assert lib.sem_ax(None, fake, fake, 3, None) == L.SEM_ERR_ARG
+    assert lib.vec_axpy(-1, 1.0, None, None, None) == L.SEM_ERR_ARG
+    assert lib.vec_dot(5, None, None, None, fake, fake, 1024, None) == L.SEM_ERR_ARG
+    assert lib.vec_dot(5, fake, fake, None, fake, fake, 0, None) == L.SEM_ERR_NOMEM
+    assert lib.sem_nlocal(None) == -1
+    assert lib.sem_destroy(None) == L.SEM_ERR_ARG
+    assert lib.vec_dot_workspace_bytes(2049) == 16

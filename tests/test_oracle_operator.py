@@ -274,3 +274,17 @@ def test_planted_geometry_mistake_is_caught():
     ref = (A @ lattice.reshape(-1))[pr.gid]
     interior = pr.mask.reshape(-1) > 0
     assert np.max(np.abs(Au[interior] - ref[interior])) > 1e-8 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("center", [0, 5, 17, 35])
+def test_patch_equals_full_mesh(center):
+    """The sampled-element route used at large sizes reproduces the full mesh."""
+    nx, ny, nz, N = 4, 3, 3, 4
+    pr = _problem(nx, ny, nz, N, 0.05)
+    u = workload.continuous_rhs(1, nx, ny, nz, N, zero_boundary=False)
+    P = op.Patch(nx, ny, nz, N, 0.05, center)
+    n3 = (N + 1) ** 3
+    up = np.concatenate([u[e * n3:(e + 1) * n3] for e in P.elements])
+    for mode, ref in (("masked", pr.ax(u)), ("local", pr.ax_local(u)),
+                      ("assembled", pr.ax_assembled(u))):
+        assert np.array_equal(P.ax_center(up, mode), ref[center])
