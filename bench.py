@@ -172,6 +172,21 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         axm_s = m0.elapsed_time(m1) / 1e3 / args.ax_reps
 
+        # ---- plain device copy of a known size (reference for HBM counters)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(10):
+            dst.copy_(src)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        copy_s = c0.elapsed_time(c1) / 1e3 / 10
+        copy_gbs = 2 * src.numel() * 8 / copy_s / 1e9
+        del src, dst
+
     E, L = A.E, A.L
     gdof = E * N ** 3
     value = gdof * timed_iters / wall / 1e9
@@ -206,6 +221,8 @@ def main(argv=None) -> int:
         "ax_local_us": ax_s * 1e6,
         "ax_masked_us": axm_s * 1e6,
         "ax_gdofs": gdof / ax_s / 1e9,
+        "copy_gbs_measured": copy_gbs,
+        "ax_frac_of_measured_copy": achieved / copy_gbs,
         "ax_masked_gdofs": gdof / axm_s / 1e9,
         "roofline": {
             "kernel": "ax_f64_kernel<8,false> (sem_ax element operator, N=7)",

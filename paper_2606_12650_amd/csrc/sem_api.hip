@@ -60,7 +60,7 @@ bool desc_valid(const sem_mesh_desc *d, std::string *why) {
   return true;
 }
 
-Box box_of(const sem_mesh_desc *d) { return Box{d->nelx, d->nely, d->nelz, d->order}; }
+Box box_of(const sem_mesh_desc *d) { return Box::make(d->nelx, d->nely, d->nelz, d->order); }
 
 Layout layout_of(const sem_mesh_desc *d) {
   const Box b = box_of(d);
@@ -81,8 +81,8 @@ Layout layout_of(const sem_mesh_desc *d) {
   o.p = take(L * sizeof(double));
   o.w = take(L * sizeof(double));
   o.part_ax = take((size_t)semk::ax_num_blocks(b) * sizeof(double));
-  o.part_rr = take((size_t)semk::vec_num_blocks(b.L()) * sizeof(double));
-  o.part_rz = take((size_t)semk::vec_num_blocks(b.L()) * sizeof(double));
+  o.part_rr = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
+  o.part_rz = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
   o.state = take(sizeof(CgState));
   o.total = at;
   return o;
@@ -159,7 +159,6 @@ void deriv_host(int N, const std::vector<double> &xs, std::vector<double> *D) {
 struct sem_ctx {
   sem_mesh_desc desc;
   Box box;
-  semk::Skeleton sk;
   Layout lay;
   char *ws;
   size_t ws_bytes;
@@ -176,13 +175,17 @@ struct sem_ctx {
 
 namespace {
 
+// One Jacobi-PCG iteration: the operator kernel (its prologue finishes the
+// previous iteration's x += alpha p and forms the new p; its epilogue leaves
+// the partials of <p, A p>), a one-group alpha step, the update kernel (which
+// pulls the assembled, masked A p from the element-local result) and a
+// one-group step for beta, the residual and the done flag.
 int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_f64(b, c->D, c->G, c->p, c->w, c->r, c->minv, c->st, c->part_ax, s));
-  SEM_HIP(semk::launch_dssum(b, c->sk, c->w, 1, &c->st->done, s));
-  SEM_HIP(semk::launch_cg_finalize_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
-  SEM_HIP(semk::launch_cg_update(b, x, c->p, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
-  SEM_HIP(semk::launch_cg_finalize_beta(c->st, c->part_rr, c->part_rz, c->n_vec_blocks, s));
+  SEM_HIP(semk::launch_ax_f64(b, c->D, c->G, c->p, c->w, c->r, c->minv, x, c->st, c->part_ax, s));
+  SEM_HIP(semk::launch_cg_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
+  SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_vec_blocks, s));
   return SEM_OK;
 }
 
@@ -253,7 +256,6 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   sem_ctx *c = new sem_ctx();
   c->desc = *desc;
   c->box = box_of(desc);
-  c->sk = semk::make_skeleton(c->box);
   c->lay = lay;
   c->ws = (char *)dev_ws;
   c->ws_bytes = ws_bytes;
@@ -269,7 +271,7 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->part_rz = (double *)(c->ws + lay.part_rz);
   c->st = (CgState *)(c->ws + lay.state);
   c->n_ax_blocks = semk::ax_num_blocks(c->box);
-  c->n_vec_blocks = semk::vec_num_blocks(c->box.L());
+  c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
   c->graph = nullptr;
 
   const int N = desc->order;
@@ -287,12 +289,11 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
     return bail(hip_fail(e, "sem_setup: upload D"));
   if ((e = hipMemcpyAsync(c->nodes, nodes.data(), nodes.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
     return bail(hip_fail(e, "sem_setup: upload nodes"));
-  if ((e = semk::launch_setup_geom(c->box, desc->deform_amp, c->D, c->nodes, c->G, c->minv, s)) != hipSuccess)
+  // element-local diagonal into r (scratch), then Minv = 1 / (sum of copies)
+  if ((e = semk::launch_setup_geom(c->box, desc->deform_amp, c->D, c->nodes, c->G, c->r, s)) != hipSuccess)
     return bail(hip_fail(e, "sem_setup: geometry kernel"));
-  if ((e = semk::launch_dssum(c->box, c->sk, c->minv, 0, nullptr, s)) != hipSuccess)
+  if ((e = semk::launch_gather(c->box, c->r, c->minv, semk::kGatherInverse, s)) != hipSuccess)
     return bail(hip_fail(e, "sem_setup: diagonal gather-scatter"));
-  if ((e = semk::launch_invert_diag(c->box, c->minv, s)) != hipSuccess)
-    return bail(hip_fail(e, "sem_setup: invert diagonal"));
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sem_setup: synchronize"));
   *out = c;
   return SEM_OK;
@@ -314,10 +315,16 @@ int sem_ax(sem_ctx *ctx, const double *u, double *w, int mode, void *stream) {
   if (mode != SEM_AX_LOCAL && mode != SEM_AX_ASSEMBLED && mode != SEM_AX_MASKED)
     return fail(SEM_ERR_ARG, "sem_ax: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
-  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
-                              nullptr, nullptr, nullptr, s));
-  if (mode != SEM_AX_LOCAL)
-    SEM_HIP(semk::launch_dssum(ctx->box, ctx->sk, w, mode == SEM_AX_MASKED ? 1 : 0, nullptr, s));
+  if (mode == SEM_AX_LOCAL) {
+    SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, s));
+    return SEM_OK;
+  }
+  // element-local result into the workspace, then the gather-scatter pull
+  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), ctx->w, nullptr,
+                              nullptr, nullptr, nullptr, nullptr, s));
+  SEM_HIP(semk::launch_gather(ctx->box, ctx->w, w,
+                              mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));
   return SEM_OK;
 }
 
@@ -339,9 +346,8 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
   h.max_iter = max_iter;
   h.rtol2 = opts->fixed_iter > 0 ? -1.0 : opts->rtol * opts->rtol;
   SEM_HIP(hipMemcpyAsync(ctx->st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
-  SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->minv, ctx->part_rz,
+  SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->minv, ctx->st, ctx->part_rz,
                                ctx->part_rr, s));
-  SEM_HIP(semk::launch_cg_finalize_init(ctx->st, ctx->part_rz, ctx->part_rr, ctx->n_vec_blocks, s));
 
   int rc = capture_graph(ctx, x, every, s);
   if (rc < 0) return rc;
@@ -359,7 +365,11 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
     launched += every;
     SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
-    if (h.done != semk::kRunning) break;
+    if (h.done != semk::kRunning) {
+      SEM_HIP(semk::launch_cg_finish(ctx->box, x, ctx->p, ctx->st, s));
+      SEM_HIP(hipStreamSynchronize(s));
+      break;
+    }
     if (launched > max_iter + every) return fail(SEM_ERR_HIP, "sem_cg: device state stopped advancing");
   }
   info->iters = h.iter;

@@ -9,6 +9,7 @@
 // of the element (element-major layout, i fastest).
 #include <hip/hip_runtime.h>
 
+#include "sem_device.h"
 #include "sem_internal.h"
 
 namespace semk {
@@ -25,32 +26,12 @@ struct AxCfg {
   static constexpr int NP = N1 * N1 * N1;
 };
 
-constexpr int next_pow2(int v) {
-  int p = 1;
-  while (p < v) p <<= 1;
-  return p;
-}
-
-// Deterministic block sum through LDS (fixed pairing, any block size T).
-template <int T>
-__device__ double block_sum_lds(double v, double *sred) {
-  sred[threadIdx.x] = v;
-  __syncthreads();
-  constexpr int P2 = next_pow2(T);
-#pragma unroll
-  for (int s = P2 / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s && (int)threadIdx.x + s < T) sred[threadIdx.x] += sred[threadIdx.x + s];
-    __syncthreads();
-  }
-  return sred[0];
-}
-
 template <int N1, bool CG>
 __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
     ax_f64_kernel(int64_t E, const double *__restrict__ Dg, const double *__restrict__ G,
                   double *u, double *__restrict__ w, const double *__restrict__ r,
-                  const double *__restrict__ minv, const CgState *__restrict__ st,
-                  double *__restrict__ part) {
+                  const double *__restrict__ minv, double *__restrict__ x,
+                  CgState *__restrict__ st, double *__restrict__ part) {
   using C = AxCfg<N1>;
   constexpr int NP = C::NP;
   constexpr int PL = N1 * N1;
@@ -75,11 +56,13 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   double g[6][N1];
   if (active) {
     if (CG) {
-      const double beta = st->beta;
+      const double beta = st->beta, alpha = st->alpha;
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         const int64_t idx = base + k * PL;
-        const double v = minv[idx] * r[idx] + beta * u[idx];
+        const double pold = u[idx];
+        x[idx] += alpha * pold;
+        const double v = minv[idx] * r[idx] + beta * pold;
         uk[k] = v;
         u[idx] = v;
       }
@@ -154,7 +137,7 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   }
   if (CG) {
     __syncthreads();  // s1 is reused as the reduction buffer
-    const double tot = block_sum_lds<C::THREADS>(acc, s1);
+    const double tot = block_sum_any<C::THREADS>(acc, s1);
     if (tid == 0) part[blockIdx.x] = tot;
   }
 }
@@ -281,17 +264,17 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
 
 template <int N1>
 hipError_t ax_dispatch(const Box &b, const double *D, const double *G, double *u, double *w,
-                       const double *r, const double *minv, const CgState *cg, double *part,
+                       const double *r, const double *minv, double *x, CgState *cg, double *part,
                        hipStream_t s) {
   using C = AxCfg<N1>;
   const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
   if (blocks == 0) return hipSuccess;
   if (cg)
     hipLaunchKernelGGL((ax_f64_kernel<N1, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
-                       b.E(), D, G, u, w, r, minv, cg, part);
+                       b.E(), D, G, u, w, r, minv, x, cg, part);
   else
     hipLaunchKernelGGL((ax_f64_kernel<N1, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
-                       s, b.E(), D, G, u, w, r, minv, cg, part);
+                       s, b.E(), D, G, u, w, r, minv, x, cg, part);
   return hipGetLastError();
 }
 
@@ -329,12 +312,12 @@ int64_t ax_num_blocks(const Box &b) {
 }
 
 hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
-                         const double *r, const double *minv, const CgState *cg, double *part,
-                         hipStream_t s) {
+                         const double *r, const double *minv, double *x, CgState *cg,
+                         double *part, hipStream_t s) {
   switch (b.N) {
 #define CASE(n) \
   case n:       \
-    return ax_dispatch<n + 1>(b, D, G, u, w, r, minv, cg, part, s);
+    return ax_dispatch<n + 1>(b, D, G, u, w, r, minv, x, cg, part, s);
     SEM_FOR_EACH_ORDER(CASE)
 #undef CASE
     default:

@@ -1,0 +1,154 @@
+// Device helpers shared by the kernel translation units: wave64 and block
+// reductions, XCD-aware tile order and the per-node facts of element-local
+// storage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sem_internal.h"
+
+namespace semk {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a block of T threads (T a multiple of 64); valid in thread 0.
+// The order is fixed: butterfly inside each wave, then waves in index order.
+template <int T>
+__device__ inline double block_sum(double v, double *sred) {
+  static_assert(T % 64 == 0, "block size must be a multiple of the wave size");
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sred[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < T / 64; ++q) t += sred[q];
+  }
+  __syncthreads();
+  return t;
+}
+
+constexpr int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Deterministic block sum through LDS for any block size T; valid in thread 0.
+template <int T>
+__device__ inline double block_sum_any(double v, double *sred) {
+  sred[threadIdx.x] = v;
+  __syncthreads();
+  constexpr int P2 = next_pow2(T);
+#pragma unroll
+  for (int s = P2 / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s && (int)threadIdx.x + s < T) sred[threadIdx.x] += sred[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double t = sred[0];
+  __syncthreads();
+  return t;
+}
+
+// Sum of n partials in a fixed order by a block of T threads; valid in
+// thread 0.  Eight independent loads per thread are in flight at a time.
+template <int T>
+__device__ inline double sum_partials(const double *__restrict__ part, int64_t n, double *sred) {
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = threadIdx.x; q < n; q += 8 * T) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t idx = q + (int64_t)u * T;
+      if (idx < n) a[u] += part[idx];
+    }
+  }
+  const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  return block_sum<T>(t, sred);
+}
+
+// Work-groups are dispatched round-robin over the 8 XCDs; this maps the
+// launch index to a tile so that each XCD walks one contiguous range of
+// tiles in order (neighbouring elements then share that XCD's L2).
+constexpr int kNumXcd = 8;
+inline int64_t xcd_grid(int64_t ntiles) { return kNumXcd * ((ntiles + kNumXcd - 1) / kNumXcd); }
+__device__ inline int64_t xcd_tile(int64_t ntiles) {
+  const int64_t per = (ntiles + kNumXcd - 1) / kNumXcd;
+  const int64_t b = blockIdx.x;
+  return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+// Position of an element-local node of a box mesh.
+template <int N1>
+struct Node {
+  int i, j, k;
+  int ex, ey, ez;
+  bool boundary;  // on a face of the box (homogeneous Dirichlet)
+  int mult;       // number of element-local copies (1, 2, 4 or 8)
+};
+
+// All index arithmetic is 32-bit: the element index is below 2^31 and the
+// divisions by nx and ny are multiply-shifts.
+template <int N1>
+__device__ inline Node<N1> node_at(const Box &b, int64_t idx) {
+  constexpr int N = N1 - 1;
+  constexpr uint32_t NP = N1 * N1 * N1;
+  const uint32_t e = (uint32_t)(idx / NP);
+  const uint32_t loc = (uint32_t)(idx - (int64_t)e * NP);
+  Node<N1> n;
+  n.i = (int)(loc % N1);
+  n.j = (int)((loc / N1) % N1);
+  n.k = (int)(loc / (N1 * N1));
+  const uint32_t eyz = b.fdx.div(e);
+  n.ex = (int)(e - eyz * (uint32_t)b.nx);
+  const uint32_t ez = b.fdy.div(eyz);
+  n.ey = (int)(eyz - ez * (uint32_t)b.ny);
+  n.ez = (int)ez;
+  n.boundary = (n.ex == 0 && n.i == 0) || (n.ex == b.nx - 1 && n.i == N) ||
+               (n.ey == 0 && n.j == 0) || (n.ey == b.ny - 1 && n.j == N) ||
+               (n.ez == 0 && n.k == 0) || (n.ez == b.nz - 1 && n.k == N);
+  const int mx = ((n.i == 0 && n.ex > 0) || (n.i == N && n.ex < b.nx - 1)) ? 2 : 1;
+  const int my = ((n.j == 0 && n.ey > 0) || (n.j == N && n.ey < b.ny - 1)) ? 2 : 1;
+  const int mz = ((n.k == 0 && n.ez > 0) || (n.k == N && n.ez < b.nz - 1)) ? 2 : 1;
+  n.mult = mx * my * mz;
+  return n;
+}
+
+// Direct stiffness summation at one node: the sum of all element-local
+// copies of the node in w, added in ascending element-local index order.
+// Along each direction a node has one copy, or two when it sits on a face
+// shared with the neighbouring element; the second copy is a fixed address
+// step away (next element, local index N -> 0).  All eight candidate loads
+// are issued together (predicated), so their latencies overlap; a missing
+// copy adds +0.0, which leaves the sum unchanged.  Every copy of a node
+// computes the same sum in the same order: the result is exactly continuous.
+template <int N1, typename T>
+__device__ inline double gather_copies(const T *__restrict__ w, const Box &b, const Node<N1> &n,
+                                       int64_t idx) {
+  constexpr int N = N1 - 1;
+  constexpr int64_t NP = (int64_t)N1 * N1 * N1;
+  const int64_t dx = NP - N;
+  const int64_t dy = (int64_t)b.nx * NP - (int64_t)N * N1;
+  const int64_t dz = (int64_t)b.nx * b.ny * NP - (int64_t)N * N1 * N1;
+  const bool sx = n.i == 0 && n.ex > 0, hx = sx || (n.i == N && n.ex < b.nx - 1);
+  const bool sy = n.j == 0 && n.ey > 0, hy = sy || (n.j == N && n.ey < b.ny - 1);
+  const bool sz = n.k == 0 && n.ez > 0, hz = sz || (n.k == N && n.ez < b.nz - 1);
+  const int64_t lo = idx - (sx ? dx : 0) - (sy ? dy : 0) - (sz ? dz : 0);
+  double v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int d = q & 1, c = (q >> 1) & 1, a = q >> 2;
+    const bool valid = (d == 0 || hx) && (c == 0 || hy) && (a == 0 || hz);
+    v[q] = valid ? (double)w[lo + (d ? dx : 0) + (c ? dy : 0) + (a ? dz : 0)] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += v[q];
+  return s;
+}
+
+}  // namespace semk

@@ -14,9 +14,36 @@ namespace semk {
 constexpr int kMinOrder = 1;
 constexpr int kMaxOrder = 12;
 
-// Box mesh dimensions and polynomial order.
+// Unsigned division by a runtime constant d >= 1 as a multiply and shift
+// (Granlund-Montgomery): q = (n * M) >> k with k = 32 + ceil(log2 d) and
+// M = ceil(2^k / d) < 2^33; exact for every n < 2^31.
+struct FastDiv {
+  uint64_t M;
+  uint32_t k;
+  uint32_t d;
+  static FastDiv make(uint32_t d) {
+    uint32_t sh = 0;
+    while ((1ull << sh) < d) ++sh;
+    FastDiv f;
+    f.k = 32 + sh;
+    f.M = ((1ull << f.k) + d - 1) / d;
+    f.d = d;
+    return f;
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const { return (uint32_t)(((uint64_t)n * M) >> k); }
+};
+
+// Box mesh dimensions and polynomial order (fdx, fdy divide by nx, ny).
 struct Box {
   int nx, ny, nz, N;
+  FastDiv fdx, fdy;
+  static Box make(int nx, int ny, int nz, int N) {
+    Box b;
+    b.nx = nx; b.ny = ny; b.nz = nz; b.N = N;
+    b.fdx = FastDiv::make((uint32_t)nx);
+    b.fdy = FastDiv::make((uint32_t)ny);
+    return b;
+  }
   __host__ __device__ int n1() const { return N + 1; }
   __host__ __device__ int64_t E() const { return (int64_t)nx * ny * nz; }
   __host__ __device__ int64_t np() const { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
@@ -32,7 +59,7 @@ struct CgState {
   int done;
   int iter;
   int max_iter;
-  int pad;
+  int done_stage;  // 2 when the last finished iteration updated r (x still owes alpha p)
   double rho;     // <r, Minv r>_c
   double alpha;
   double beta;
@@ -43,14 +70,6 @@ struct CgState {
   double tol2;    // rtol2 * bnorm2
 };
 
-// Skeleton categories for the gather-scatter: nodes whose lattice index is a
-// multiple of N in the directions of the bit set c (bit 0 = x, 1 = y, 2 = z).
-// start[c-1] .. start[c]-1 are the thread ids of category c (c = 1..7).
-struct Skeleton {
-  int64_t start[8];
-};
-Skeleton make_skeleton(const Box &b);
-
 // Launch shapes of the element kernels (shared by host sizing code).
 int ax_elements_per_block(int N);
 int64_t ax_num_blocks(const Box &b);
@@ -58,6 +77,14 @@ constexpr int kVecThreads = 256;
 constexpr int kVecItems = 8;   // entries per thread of the streaming kernels
 constexpr int64_t kVecTile = (int64_t)kVecThreads * kVecItems;
 inline int64_t vec_num_blocks(int64_t n) { return (n + kVecTile - 1) / kVecTile; }
+// Launch size (and partial count) of the element-local streaming kernels:
+// tiles padded to a multiple of the XCD count.
+inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) / 8); }
+
+// What the gather kernel writes at a node: the sum of its copies
+// (assembled), the same with box-boundary nodes zeroed (masked), or the
+// Jacobi inverse 1/sum with boundary nodes zeroed (inverse).
+enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse = 2 };
 
 // ---------------------------------------------------------------- launchers
 // All return the hipError_t of the launch (hipGetLastError after it).
@@ -65,34 +92,38 @@ inline int64_t vec_num_blocks(int64_t n) { return (n + kVecTile - 1) / kVecTile;
 // G (E x 6 x np) and the element-local Jacobi diagonal (L) of box b.
 hipError_t launch_setup_geom(const Box &b, double amp, const double *D, const double *nodes,
                              double *G, double *diag_local, hipStream_t s);
-// In place: d <- (interior node) ? 1/d : 0.
-hipError_t launch_invert_diag(const Box &b, double *d, hipStream_t s);
 // Inverse multiplicity c as an L-vector.
 hipError_t launch_fill_c(const Box &b, double *c, hipStream_t s);
 
-// w = A_L u.  With cg != null the CG prologue p <- Minv r + beta p runs first
-// (u is p, updated in place) and per-block partial sums of p.w go to part.
+// w = A_L u.  With cg != null (a CG iteration) a prologue first finishes the
+// previous iteration, x += alpha p, then forms p <- Minv r + beta p (u is p,
+// updated in place), and per-block partial sums of p.w go to part
+// (ax_num_blocks of them).
 hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
-                         const double *r, const double *minv, const CgState *cg, double *part,
-                         hipStream_t s);
+                         const double *r, const double *minv, double *x, CgState *cg,
+                         double *part, hipStream_t s);
 
-// Gather-scatter over copies of shared nodes; masked != 0 zeroes boundary
-// nodes.  Skipped when *done != 0 (done may be null).
-hipError_t launch_dssum(const Box &b, const Skeleton &sk, double *w, int masked, const int *done,
-                        hipStream_t s);
+// out = the copies of every node of wl summed (GatherMode); wl != out.
+hipError_t launch_gather(const Box &b, const double *wl, double *out, int mode, hipStream_t s);
 
-// CG pieces (all skip when the state's done flag is set).
+// CG start: x = 0, r = mask o b, p = 0, partials of <r, Minv r>_c and
+// ||b||_c^2; then a one-group launch sets rho, ||b||_c and the tolerance.
 hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r, double *p,
-                          const double *minv, double *part_rz, double *part_bb, hipStream_t s);
-hipError_t launch_cg_finalize_init(CgState *st, const double *part_rz, const double *part_bb,
-                                   int64_t nparts, hipStream_t s);
-hipError_t launch_cg_finalize_alpha(CgState *st, const double *part_pw, int64_t nparts,
-                                    hipStream_t s);
-hipError_t launch_cg_update(const Box &b, double *x, const double *p, double *r, const double *w,
-                            const double *minv, const CgState *st, double *part_rr,
-                            double *part_rz, hipStream_t s);
-hipError_t launch_cg_finalize_beta(CgState *st, const double *part_rr, const double *part_rz,
-                                   int64_t nparts, hipStream_t s);
+                          const double *minv, CgState *st, double *part_a, double *part_b,
+                          hipStream_t s);
+// CG update with the gather of w fused in: r -= alpha mask o QQ^T w,
+// partials of ||r||_c^2 and <r, Minv r>_c.  Skipped when done.
+hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
+                            CgState *st, double *part_rr, double *part_rz, hipStream_t s);
+// After the last iteration: x += alpha p if that iteration's update ran.
+hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
+                            hipStream_t s);
+// One-group launches that finish the reductions and advance the scalars:
+// alpha = rho / <p, A p> (breakdown check), and after the update
+// iteration count, ||r||_c, rho, beta and the done flag.
+hipError_t launch_cg_alpha(CgState *st, const double *part_pap, int64_t n, hipStream_t s);
+hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part_rz, int64_t n,
+                          hipStream_t s);
 
 // Generic vectors.
 hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);
