@@ -34,7 +34,7 @@ METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latenc
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_internal.h"):
+    for f in ("sem_ax.hip", "sem_internal.h", "sem_device.h"):
         with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
