@@ -187,6 +187,39 @@ def main(argv=None) -> int:
         copy_gbs = 2 * src.numel() * 8 / copy_s / 1e9
         del src, dst
 
+        # ---- precision form: inner-outer CG with the FP32 / BF16 operator
+        mixed = {}
+        x64 = x.clone()
+        c_w = A.export(sem._lib.SEM_FIELD_C)
+        for prec in ("f32", "bf16"):
+            Am = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=dev)
+            xm = torch.empty_like(b)
+            for _ in range(max(1, args.warmup)):
+                Am.cg(b, xm, rtol=rtol, mixed=True)
+            torch.cuda.synchronize()
+            msteps = max(1, args.steps // 2)
+            t0m = time.perf_counter()
+            inner = outer = 0
+            for _ in range(msteps):
+                _, rm = Am.cg(b, xm, rtol=rtol, mixed=True)
+                inner += rm.iters
+                outer += rm.outer_iters
+            torch.cuda.synchronize()
+            wm = time.perf_counter() - t0m
+            err = math.sqrt(float((c_w * (xm - x64) ** 2).sum()) / float((c_w * x64 ** 2).sum()))
+            mixed[prec] = {
+                "solves_per_s": msteps / wm,
+                "ms_per_solve": wm / msteps * 1e3,
+                "inner_iters_per_solve": inner / msteps,
+                "outer_iters_per_solve": outer / msteps,
+                "rel_res_fp64": rm.rel_res,
+                "rel_err_vs_fp64_solution": err,
+                "status": rm.status,
+            }
+            print(f"[bench] mixed {prec}: {mixed[prec]}", file=sys.stderr, flush=True)
+            del Am, xm
+        torch.cuda.synchronize()
+
     E, L = A.E, A.L
     gdof = E * N ** 3
     value = gdof * timed_iters / wall / 1e9
@@ -215,6 +248,7 @@ def main(argv=None) -> int:
             "E": E, "N": N, "L": L, "gdof_per_iter": gdof, "rtol": rtol,
         },
         "solves_per_s": args.steps / wall,
+        "mixed": {k: dict(v, speedup_vs_fp64=v["solves_per_s"] / (args.steps / wall)) for k, v in mixed.items()},
         "cg_iters_per_solve": timed_iters / args.steps,
         "cg_event_ms_per_step": ev_ms / args.steps,
         "cg_hbm_floor_frac": cg_bytes_per_iter * timed_iters / wall / 1e9 / HBM_PEAK_GBS,
@@ -225,7 +259,7 @@ def main(argv=None) -> int:
         "ax_frac_of_measured_copy": achieved / copy_gbs,
         "ax_masked_gdofs": gdof / axm_s / 1e9,
         "roofline": {
-            "kernel": "ax_f64_kernel<8,false> (sem_ax element operator, N=7)",
+            "kernel": "ax_kernel<8, PrecF64, false> (sem_ax element operator, N=7)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -107,16 +107,30 @@ int64_t sem_nlocal(const sem_ctx *ctx);
  * doubles on the device, u != w.  u may be discontinuous for SEM_AX_LOCAL. */
 int sem_ax(sem_ctx *ctx, const double *u_dev, double *w_dev, int mode, void *stream);
 
+/* w = A_lo u with the low-precision operator copy of a mesh set up with
+ * desc.lowprec = SEM_F32 or SEM_BF16 (else SEM_ERR_ARG).  u and w are FP32
+ * L-vectors on the device, u != w; `mode` as for sem_ax.  A_lo uses D and G
+ * rounded to the copy's type (round to nearest even); in SEM_BF16 both
+ * contraction inputs (u and the G-weighted gradient) are also rounded to
+ * bfloat16, so products are exact and only the FP32 accumulation rounds.
+ * This is the inner operator of the mixed-precision sem_cg. */
+int sem_ax_lowp(sem_ctx *ctx, const float *u_dev, float *w_dev, int mode, void *stream);
+
 /* Options of sem_cg. */
 typedef struct {
   double rtol;         /* stop when ||r||_c <= rtol*||b||_c (tolerance mode)    */
   int32_t max_iter;    /* iteration cap in tolerance mode (<=0: 20000)          */
   int32_t fixed_iter;  /* > 0: run exactly this many iterations, no tolerance   */
-  int32_t mixed;       /* 0: FP64 PCG.  1: inner-outer refinement with the
-                          low-precision operator copy (needs desc.lowprec)      */
+  int32_t mixed;       /* 0: FP64 PCG.  1: inner-outer refinement: an inner
+                          Jacobi-PCG with the low-precision operator copy on
+                          FP32 vectors (needs desc.lowprec) solves
+                          A_lo e = r/||r||_c to inner_rtol; then x += ||r||_c e
+                          and r = b - A x in FP64; repeat until rtol.
+                          max_iter then caps the outer steps (<=0: 50).     */
   int32_t check_every; /* iterations per captured graph replay (<=0: 25)        */
-  double inner_rtol;   /* mixed: inner relative tolerance (<=0: 1e-3)           */
-  int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 200)  */
+  double inner_rtol;   /* mixed: inner relative tolerance (<=0: 1e-3 for SEM_F32,
+                          1e-2 for SEM_BF16)                                   */
+  int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 1000) */
   int32_t reserved;
 } sem_cg_opts;
 

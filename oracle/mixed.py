@@ -4,8 +4,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper fixes no precision.  The precision form evaluates the derivative
 contractions with D, G and the input rounded to FP32 or BF16 (round to nearest
-even) and accumulates in FP32, inside an inner CG whose result corrects an
-FP64 outer iterate:
+even) and accumulates in FP32.  In BF16 mode both inputs of each contraction
+are bfloat16 (the operand u of the gradient and the G-weighted gradient that
+enters the transposed contraction), as a bfloat16 matrix-core contraction
+consumes them; all products are then exact in FP32.  The operator sits inside
+an inner CG whose result corrects an FP64 outer iterate:
 
     x = 0; r = b
     repeat until ||r||_c <= rtol ||b||_c:
@@ -47,10 +50,27 @@ def rounder(prec: str):
 
 
 def ax_local_rounded(problem, u, prec: str):
-    """A_L u evaluated exactly (FP64) with D, G and u rounded to ``prec``:
-    the value a low-precision kernel approximates up to FP32 accumulation."""
+    """A_L u evaluated in FP64 with D, G and u rounded to ``prec`` (and, in
+    BF16 mode, the G-weighted gradient rounded to bfloat16 before the
+    transposed contraction): the value a low-precision kernel approximates
+    up to its FP32 accumulation."""
     rd = rounder(prec)
-    return ax_local(rd(problem.shape4(u)), rd(problem.D), rd(problem.G))
+    D = rd(problem.D)
+    G = rd(problem.G)
+    v = rd(problem.shape4(u))
+    ur = np.einsum("il,ekjl->ekji", D, v)
+    us = np.einsum("jl,ekli->ekji", D, v)
+    ut = np.einsum("kl,elji->ekji", D, v)
+    g = [G[:, q] for q in range(6)]
+    wr = g[0] * ur + g[1] * us + g[2] * ut
+    ws = g[1] * ur + g[3] * us + g[4] * ut
+    wt = g[2] * ur + g[4] * us + g[5] * ut
+    if prec == "bf16":
+        wr, ws, wt = round_bf16(wr), round_bf16(ws), round_bf16(wt)
+    out = np.einsum("li,ekjl->ekji", D, wr)
+    out += np.einsum("lj,ekli->ekji", D, ws)
+    out += np.einsum("lk,elji->ekji", D, wt)
+    return out
 
 
 def ax_local_abs_bound(problem, u, prec: str):
@@ -85,6 +105,8 @@ def inner_outer(problem, b, prec: str = "f32", rtol=1e-8, eta=1e-3, max_inner=20
         wr = g[0] * ur + g[1] * us + g[2] * ut
         ws = g[1] * ur + g[3] * us + g[4] * ut
         wt = g[2] * ur + g[4] * us + g[5] * ut
+        if prec == "bf16":
+            wr, ws, wt = (rd(t.astype(np.float64)).astype(np.float32) for t in (wr, ws, wt))
         out = np.einsum("li,ekjl->ekji", D32, wr)
         out = out + np.einsum("lj,ekli->ekji", D32, ws)
         out = out + np.einsum("lk,elji->ekji", D32, wt)

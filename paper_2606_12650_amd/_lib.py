@@ -27,6 +27,7 @@ SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2
 EXPORTS = (
     "sem_workspace_bytes", "sem_setup", "sem_destroy", "sem_nlocal", "sem_ax", "sem_cg",
     "vec_axpy", "vec_dot_workspace_bytes", "vec_dot", "sem_export", "sem_last_error",
+    "sem_ax_lowp",
 )
 
 
@@ -67,6 +68,7 @@ def _declare(lib):
         "sem_destroy": (ctypes.c_int, [vp]),
         "sem_nlocal": (i64, [vp]),
         "sem_ax": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
+        "sem_ax_lowp": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp]),
         "sem_cg": (ctypes.c_int, [vp, vp, vp, P(SemCgOpts), P(SemCgInfo), vp]),
         "vec_axpy": (ctypes.c_int, [i64, dbl, vp, vp, vp]),
         "vec_dot_workspace_bytes": (sz, [i64]),

@@ -29,6 +29,9 @@ COMMON = [
     "-Wall",
     "-Wno-unused-variable",
     "-Wno-unused-function",
+    # contractions only within one source expression: results do not depend
+    # on the inlining context, so batched and single solves give equal bits
+    "-ffp-contract=on",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,

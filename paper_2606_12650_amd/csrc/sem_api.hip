@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "sem_device.h"
 #include "sem_internal.h"
 
 using semk::Box;
@@ -37,9 +38,12 @@ int hip_fail(hipError_t e, const char *what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Byte offsets of every buffer inside the caller's workspace.
+// Byte offsets of every buffer inside the caller's workspace.  The low-
+// precision block (Dlo .. state_in) exists only when desc.lowprec != SEM_F64.
 struct Layout {
-  size_t D, nodes, G, minv, r, p, w, part_ax, part_rr, part_rz, state, total;
+  size_t D, nodes, G, minv, r, p, w, part_ax, part_rr, part_rz, state;
+  size_t Dlo, Glo, minv32, e, rin, pin, win, state_in;
+  size_t total;
 };
 
 bool desc_valid(const sem_mesh_desc *d, std::string *why) {
@@ -80,10 +84,22 @@ Layout layout_of(const sem_mesh_desc *d) {
   o.r = take(L * sizeof(double));
   o.p = take(L * sizeof(double));
   o.w = take(L * sizeof(double));
-  o.part_ax = take((size_t)semk::ax_num_blocks(b) * sizeof(double));
+  o.part_ax = take((size_t)b.E() * sizeof(double));  // per-element p.Ap
   o.part_rr = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
   o.part_rz = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
   o.state = take(sizeof(CgState));
+  o.Dlo = o.Glo = o.minv32 = o.e = o.rin = o.pin = o.win = o.state_in = 0;
+  if (d->lowprec != SEM_F64) {
+    const size_t gbytes = d->lowprec == SEM_BF16 ? 2 : 4;
+    o.Dlo = take(n1 * n1 * sizeof(float));
+    o.Glo = take(6 * L * gbytes);
+    o.minv32 = take(L * sizeof(float));
+    o.e = take(L * sizeof(float));
+    o.rin = take(L * sizeof(float));
+    o.pin = take(L * sizeof(float));
+    o.win = take(L * sizeof(float));
+    o.state_in = take(sizeof(CgState));
+  }
   o.total = at;
   return o;
 }
@@ -164,13 +180,18 @@ struct sem_ctx {
   size_t ws_bytes;
   double *D, *nodes, *G, *minv, *r, *p, *w, *part_ax, *part_rr, *part_rz;
   CgState *st;
-  int64_t n_ax_blocks, n_vec_blocks;
+  // low-precision copy (null when desc.lowprec == SEM_F64)
+  float *Dlo, *minv32, *e, *rin, *pin, *win;
+  void *Glo;
+  CgState *st_in;
+  int64_t n_ax_blocks, n_vec_blocks;  // partial counts: elements, streaming tiles
   CgState host_state;  // staging for the state upload / status reads
-  // cached graph of `graph_iters` CG iterations writing into graph_x
-  hipGraphExec_t graph;
-  hipStream_t graph_stream;
-  double *graph_x;
-  int graph_iters;
+  CgState host_inner;
+  // cached graphs: [0] FP64 CG iterations into graph_x, [1] inner iterations
+  hipGraphExec_t graph[2];
+  hipStream_t graph_stream[2];
+  double *graph_x[2];
+  int graph_iters[2];
 };
 
 namespace {
@@ -189,27 +210,43 @@ int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   return SEM_OK;
 }
 
-void drop_graph(sem_ctx *c) {
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
-  c->graph = nullptr;
-  c->graph_stream = nullptr;
-  c->graph_x = nullptr;
-  c->graph_iters = 0;
+// One iteration of the inner (low-precision) Jacobi-PCG: the same four steps
+// on FP32 vectors with the rounded operator; the inner correction e plays x.
+int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
+  const Box &b = c->box;
+  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->Dlo, c->Glo, c->pin, c->win, c->rin, c->minv32,
+                               c->e, c->st_in, c->part_ax, s));
+  SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
+  SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_vec_blocks, s));
+  return SEM_OK;
 }
 
-// Capture `iters` CG iterations on stream s into c->graph.  Returns SEM_OK, or
-// a positive value when capture is not possible (the caller then launches
-// directly), or a negative error.
-int capture_graph(sem_ctx *c, double *x, int iters, hipStream_t s) {
-  if (c->graph && c->graph_stream == s && c->graph_x == x && c->graph_iters == iters) return SEM_OK;
-  drop_graph(c);
+typedef int (*enqueue_fn)(sem_ctx *, double *, hipStream_t);
+
+void drop_graph(sem_ctx *c, int slot) {
+  if (c->graph[slot]) (void)hipGraphExecDestroy(c->graph[slot]);
+  c->graph[slot] = nullptr;
+  c->graph_stream[slot] = nullptr;
+  c->graph_x[slot] = nullptr;
+  c->graph_iters[slot] = 0;
+}
+
+// Capture `iters` iterations of `fn` on stream s into graph slot `slot`.
+// Returns SEM_OK, or a positive value when capture is not possible (the
+// caller then launches directly), or a negative error.
+int capture_graph(sem_ctx *c, int slot, enqueue_fn fn, double *x, int iters, hipStream_t s) {
+  if (c->graph[slot] && c->graph_stream[slot] == s && c->graph_x[slot] == x &&
+      c->graph_iters[slot] == iters)
+    return SEM_OK;
+  drop_graph(c, slot);
   if (s == nullptr) return 1;  // the legacy null stream cannot be captured
   if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
   int rc = SEM_OK;
-  for (int it = 0; it < iters && rc == SEM_OK; ++it) rc = enqueue_cg_iteration(c, x, s);
+  for (int it = 0; it < iters && rc == SEM_OK; ++it) rc = fn(c, x, s);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   if (rc != SEM_OK) {
@@ -221,11 +258,36 @@ int capture_graph(sem_ctx *c, double *x, int iters, hipStream_t s) {
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-  c->graph = ex;
-  c->graph_stream = s;
-  c->graph_x = x;
-  c->graph_iters = iters;
+  c->graph[slot] = ex;
+  c->graph_stream[slot] = s;
+  c->graph_x[slot] = x;
+  c->graph_iters[slot] = iters;
   return SEM_OK;
+}
+
+// Run iterations of `fn` (graph replays of `every`, or direct launches)
+// until the device state `st` reports done; `host` receives the state.
+int run_until_done(sem_ctx *c, int slot, enqueue_fn fn, double *x, CgState *st, CgState *host,
+                   int every, int max_iter, hipStream_t s) {
+  int rc = capture_graph(c, slot, fn, x, every, s);
+  if (rc < 0) return rc;
+  const bool use_graph = (rc == SEM_OK);
+  int launched = 0;
+  for (;;) {
+    if (use_graph) {
+      SEM_HIP(hipGraphLaunch(c->graph[slot], s));
+    } else {
+      for (int it = 0; it < every; ++it) {
+        rc = fn(c, x, s);
+        if (rc != SEM_OK) return rc;
+      }
+    }
+    launched += every;
+    SEM_HIP(hipMemcpyAsync(host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    if (host->done != semk::kRunning) return SEM_OK;
+    if (launched > max_iter + every) return fail(SEM_ERR_HIP, "sem_cg: device state stopped advancing");
+  }
 }
 
 }  // namespace
@@ -270,9 +332,23 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->part_rr = (double *)(c->ws + lay.part_rr);
   c->part_rz = (double *)(c->ws + lay.part_rz);
   c->st = (CgState *)(c->ws + lay.state);
-  c->n_ax_blocks = semk::ax_num_blocks(c->box);
+  c->n_ax_blocks = c->box.E();
   c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
-  c->graph = nullptr;
+  for (int slot = 0; slot < 2; ++slot) {
+    c->graph[slot] = nullptr;
+    c->graph_stream[slot] = nullptr;
+    c->graph_x[slot] = nullptr;
+    c->graph_iters[slot] = 0;
+  }
+  const bool lowp = desc->lowprec != SEM_F64;
+  c->Dlo = lowp ? (float *)(c->ws + lay.Dlo) : nullptr;
+  c->Glo = lowp ? (void *)(c->ws + lay.Glo) : nullptr;
+  c->minv32 = lowp ? (float *)(c->ws + lay.minv32) : nullptr;
+  c->e = lowp ? (float *)(c->ws + lay.e) : nullptr;
+  c->rin = lowp ? (float *)(c->ws + lay.rin) : nullptr;
+  c->pin = lowp ? (float *)(c->ws + lay.pin) : nullptr;
+  c->win = lowp ? (float *)(c->ws + lay.win) : nullptr;
+  c->st_in = lowp ? (CgState *)(c->ws + lay.state_in) : nullptr;
 
   const int N = desc->order;
   std::vector<double> xs, wq, D;
@@ -294,6 +370,21 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
     return bail(hip_fail(e, "sem_setup: geometry kernel"));
   if ((e = semk::launch_gather(c->box, c->r, c->minv, semk::kGatherInverse, s)) != hipSuccess)
     return bail(hip_fail(e, "sem_setup: diagonal gather-scatter"));
+  // low-precision copy: D rounded on the host, G and Minv rounded on the GPU
+  std::vector<float> Dlo(D.size());
+  if (lowp) {
+    for (size_t q = 0; q < D.size(); ++q) {
+      const float f = (float)D[q];
+      Dlo[q] = desc->lowprec == SEM_BF16 ? semk::bf16_value(semk::bf16_bits(f)) : f;
+    }
+    if ((e = hipMemcpyAsync(c->Dlo, Dlo.data(), Dlo.size() * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
+      return bail(hip_fail(e, "sem_setup: upload rounded D"));
+    const int64_t L = c->box.L();
+    if ((e = semk::launch_convert_g(desc->lowprec, 6 * L, c->G, c->Glo, s)) != hipSuccess)
+      return bail(hip_fail(e, "sem_setup: round G"));
+    if ((e = semk::launch_convert_g(SEM_F32, L, c->minv, c->minv32, s)) != hipSuccess)
+      return bail(hip_fail(e, "sem_setup: round Minv"));
+  }
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return bail(hip_fail(e, "sem_setup: synchronize"));
   *out = c;
   return SEM_OK;
@@ -301,7 +392,8 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
 
 int sem_destroy(sem_ctx *ctx) {
   if (!ctx) return fail(SEM_ERR_ARG, "sem_destroy: null handle");
-  drop_graph(ctx);
+  drop_graph(ctx, 0);
+  drop_graph(ctx, 1);
   delete ctx;
   return SEM_OK;
 }
@@ -333,55 +425,93 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
   if (!ctx) return fail(SEM_ERR_ARG, "sem_cg: null handle");
   if (!b || !x || !opts || !info) return fail(SEM_ERR_ARG, "sem_cg: null argument");
   if (b == x) return fail(SEM_ERR_ARG, "sem_cg: b and x must differ");
-  if (opts->mixed) return fail(SEM_ERR_UNSUPPORTED, "sem_cg: mixed precision is not available in this build");
+  if (opts->mixed && ctx->desc.lowprec == SEM_F64)
+    return fail(SEM_ERR_ARG, "sem_cg: mixed precision needs a mesh set up with lowprec SEM_F32 or SEM_BF16");
+  if (opts->mixed && opts->fixed_iter > 0)
+    return fail(SEM_ERR_ARG, "sem_cg: mixed precision runs in tolerance mode only");
   if (opts->fixed_iter <= 0 && !(opts->rtol > 0.0))
     return fail(SEM_ERR_ARG, "sem_cg: rtol must be > 0 unless fixed_iter > 0");
   hipStream_t s = (hipStream_t)stream;
   const int max_iter = opts->fixed_iter > 0 ? opts->fixed_iter : (opts->max_iter > 0 ? opts->max_iter : 20000);
   int every = opts->check_every > 0 ? opts->check_every : 25;
-  if (every > max_iter) every = max_iter;
 
   CgState &h = ctx->host_state;
   std::memset(&h, 0, sizeof(h));
-  h.max_iter = max_iter;
+  h.max_iter = opts->mixed ? (opts->max_iter > 0 ? opts->max_iter : 50) : max_iter;
   h.rtol2 = opts->fixed_iter > 0 ? -1.0 : opts->rtol * opts->rtol;
   SEM_HIP(hipMemcpyAsync(ctx->st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
   SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->minv, ctx->st, ctx->part_rz,
                                ctx->part_rr, s));
-
-  int rc = capture_graph(ctx, x, every, s);
-  if (rc < 0) return rc;
-  const bool use_graph = (rc == SEM_OK);
-  int launched = 0;
-  for (;;) {
-    if (use_graph) {
-      SEM_HIP(hipGraphLaunch(ctx->graph, s));
-    } else {
-      for (int it = 0; it < every; ++it) {
-        rc = enqueue_cg_iteration(ctx, x, s);
-        if (rc != SEM_OK) return rc;
-      }
-    }
-    launched += every;
+  int status = SEM_OK;
+  if (!opts->mixed) {
+    if (every > max_iter) every = max_iter;
+    int rc = run_until_done(ctx, 0, enqueue_cg_iteration, x, ctx->st, &h, every, max_iter, s);
+    if (rc != SEM_OK) return rc;
+    SEM_HIP(semk::launch_cg_finish(ctx->box, x, ctx->p, ctx->st, s));
+    SEM_HIP(hipStreamSynchronize(s));
+    info->iters = h.iter;
+    info->outer_iters = 0;
+  } else {
+    // Inner-outer refinement: inner Jacobi-PCG with the rounded operator on
+    // FP32 vectors, outer FP64 true residual and update.
+    // defaults measured on the 32^3, N = 7 mesh: restarts cost convergence,
+    // so the inner solve runs to a moderate tolerance with a generous cap
+    const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol
+                                              : (ctx->desc.lowprec == SEM_BF16 ? 1e-2 : 1e-3);
+    const int inner_max = opts->inner_max > 0 ? opts->inner_max : 1000;
+    if (every > inner_max) every = inner_max;
+    const Box &bx = ctx->box;
+    int inner_total = 0;
     SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     SEM_HIP(hipStreamSynchronize(s));
-    if (h.done != semk::kRunning) {
-      SEM_HIP(semk::launch_cg_finish(ctx->box, x, ctx->p, ctx->st, s));
+    while (h.done == semk::kRunning) {
+      SEM_HIP(semk::launch_inner_start(bx, ctx->r, ctx->st, ctx->st_in, eta * eta, inner_max, ctx->rin,
+                                       ctx->e, ctx->pin, ctx->minv32, ctx->part_rz, ctx->part_rr, s));
+      CgState &hi = ctx->host_inner;
+      int rc = run_until_done(ctx, 1, enqueue_inner_iteration, nullptr, ctx->st_in, &hi, every,
+                              inner_max, s);
+      if (rc != SEM_OK) return rc;
+      inner_total += hi.iter;
+      SEM_HIP(semk::launch_cg_finish_f32(bx, ctx->e, ctx->pin, ctx->st_in, s));
+      SEM_HIP(semk::launch_outer_update(bx, x, ctx->e, ctx->st, s));
+      SEM_HIP(semk::launch_ax_f64(bx, ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
+                                  nullptr, s));
+      SEM_HIP(semk::launch_outer_step(bx, x, ctx->e, b, ctx->w, ctx->r, ctx->st, ctx->part_rr, s));
+      SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
       SEM_HIP(hipStreamSynchronize(s));
-      break;
+      if (hi.iter == 0 && h.done == semk::kRunning) {
+        h.done = semk::kBreakdown;  // the inner solver made no progress
+        break;
+      }
     }
-    if (launched > max_iter + every) return fail(SEM_ERR_HIP, "sem_cg: device state stopped advancing");
+    info->iters = inner_total;
+    info->outer_iters = h.iter;
   }
-  info->iters = h.iter;
-  info->outer_iters = 0;
   info->rel_res = h.bnorm2 > 0.0 ? std::sqrt(h.rnorm2 / h.bnorm2) : 0.0;
-  int status = SEM_OK;
   if (h.done == semk::kBreakdown) status = SEM_ERR_BREAKDOWN;
   else if (h.done == semk::kMaxIter && opts->fixed_iter <= 0) status = SEM_ERR_NOTCONV;
   info->status = status;
-  if (status == SEM_ERR_BREAKDOWN) g_last_error = "sem_cg: breakdown (p^T A p <= 0 or non-finite)";
+  if (status == SEM_ERR_BREAKDOWN) g_last_error = "sem_cg: breakdown (p^T A p <= 0, non-finite, or no inner progress)";
   if (status == SEM_ERR_NOTCONV) g_last_error = "sem_cg: iteration cap reached";
   return status;
+}
+
+int sem_ax_lowp(sem_ctx *ctx, const float *u, float *w, int mode, void *stream) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_ax_lowp: null handle");
+  if (ctx->desc.lowprec == SEM_F64)
+    return fail(SEM_ERR_ARG, "sem_ax_lowp: the mesh was set up without a low-precision copy");
+  if (!u || !w) return fail(SEM_ERR_ARG, "sem_ax_lowp: null vector");
+  if (u == w) return fail(SEM_ERR_ARG, "sem_ax_lowp: u and w must differ");
+  if (mode != SEM_AX_LOCAL && mode != SEM_AX_ASSEMBLED && mode != SEM_AX_MASKED)
+    return fail(SEM_ERR_ARG, "sem_ax_lowp: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
+  hipStream_t s = (hipStream_t)stream;
+  float *dst = mode == SEM_AX_LOCAL ? w : ctx->win;
+  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->Dlo, ctx->Glo, const_cast<float *>(u),
+                               dst, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  if (mode != SEM_AX_LOCAL)
+    SEM_HIP(semk::launch_gather_f32(ctx->box, ctx->win, w,
+                                    mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));
+  return SEM_OK;
 }
 
 int vec_axpy(int64_t n, double alpha, const double *x, double *y, void *stream) {

@@ -13,108 +13,131 @@
 #include "sem_internal.h"
 
 namespace semk {
-namespace {
 
 template <int N1>
-struct AxCfg {
-  // elements per work-group: about 128 threads per group
-  static constexpr int EPB = (N1 * N1 >= 128) ? 1 : (128 / (N1 * N1));
-  static constexpr int THREADS = N1 * N1 * EPB;
+struct AxTile {
   static constexpr int P = N1 + 1;      // padded row (LDS bank spread)
   static constexpr int PLANE = N1 * P;  // one k-plane of the padded tile
   static constexpr int TILE = N1 * PLANE;
   static constexpr int NP = N1 * N1 * N1;
 };
 
-template <int N1, bool CG>
-__global__ void __launch_bounds__(AxCfg<N1>::THREADS)
-    ax_f64_kernel(int64_t E, const double *__restrict__ Dg, const double *__restrict__ G,
-                  double *u, double *__restrict__ w, const double *__restrict__ r,
-                  const double *__restrict__ minv, double *__restrict__ x,
-                  CgState *__restrict__ st, double *__restrict__ part) {
-  using C = AxCfg<N1>;
-  constexpr int NP = C::NP;
+namespace {
+
+template <int N1>
+struct AxCfg {
+  // elements per work-group of the per-order kernel: about 128 threads
+  static constexpr int EPB = (N1 * N1 >= 128) ? 1 : (128 / (N1 * N1));
+  static constexpr int THREADS = N1 * N1 * EPB;
+};
+
+}  // namespace
+
+// The operator on one tile of EPB consecutive elements starting at e0,
+// computed by the first N1*N1*EPB threads of the work-group (any others
+// only join the barriers).  Shared by the per-order kernels below and the
+// batched persistent kernel, so both produce the same bits.
+//   CG: prologue x += alpha p_old, p = Minv r + beta p_old (u is p), and the
+//   per-element sums of p.(A_L p) go to part_el[e] (summed in a fixed tree).
+// sD: N1*N1, s1/s2: EPB * AxTile<N1>::TILE values of TC, sred: blockDim
+// doubles, all in LDS.
+template <int N1, int EPB, class P, bool CG>
+__device__ __forceinline__ void ax_tile(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
+                                        const typename P::TG *__restrict__ G, typename P::TV *u,
+                                        typename P::TV *__restrict__ w,
+                                        const typename P::TV *__restrict__ r,
+                                        const typename P::TV *__restrict__ minv,
+                                        typename P::TV *__restrict__ x, double alpha_d, double beta_d,
+                                        double *__restrict__ part_el, typename P::TC *sD,
+                                        typename P::TC *s1, typename P::TC *s2, double *sred) {
+  using T = AxTile<N1>;
+  using TV = typename P::TV;
+  using TC = typename P::TC;
+  constexpr int NP = T::NP;
   constexpr int PL = N1 * N1;
-  __shared__ double sD[N1 * N1];
-  __shared__ double s1[C::EPB * C::TILE];
-  __shared__ double s2[C::EPB * C::TILE];
-
-  if (CG && st->done) return;  // uniform: converged solves skip all work
-
   const int tid = threadIdx.x;
   const int el = tid / PL;
   const int ij = tid - el * PL;
   const int i = ij % N1;
   const int j = ij / N1;
-  const int64_t e = (int64_t)blockIdx.x * C::EPB + el;
-  const bool active = e < E;
+  const int64_t e = e0 + el;
+  const bool active = el < EPB && e < E;
 
-  for (int t = tid; t < N1 * N1; t += C::THREADS) sD[t] = Dg[t];
+  for (int t = tid; t < N1 * N1; t += blockDim.x) sD[t] = Dg[t];
 
   const int64_t base = e * NP + ij;
-  double uk[N1];
-  double g[6][N1];
+  TC uk[N1];  // the operand (p in CG), in the contraction type
+  TC g[6][N1];
   if (active) {
     if (CG) {
-      const double beta = st->beta, alpha = st->alpha;
+      const TV beta = (TV)beta_d, alpha = (TV)alpha_d;
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         const int64_t idx = base + k * PL;
-        const double pold = u[idx];
+        const TV pold = u[idx];
         x[idx] += alpha * pold;
-        const double v = minv[idx] * r[idx] + beta * pold;
-        uk[k] = v;
+        const TV v = minv[idx] * r[idx] + beta * pold;
+        uk[k] = (TC)v;
         u[idx] = v;
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < N1; ++k) uk[k] = u[base + k * PL];
+      for (int k = 0; k < N1; ++k) uk[k] = (TC)u[base + k * PL];
     }
-    const double *Ge = G + e * 6 * NP + ij;
+    const typename P::TG *Ge = G + e * 6 * NP + ij;
 #pragma unroll
     for (int q = 0; q < 6; ++q)
 #pragma unroll
-      for (int k = 0; k < N1; ++k) g[q][k] = Ge[q * NP + k * PL];
+      for (int k = 0; k < N1; ++k) g[q][k] = load_g<P>(Ge + q * NP + k * PL);
   } else {
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      uk[k] = 0.0;
+      uk[k] = (TC)0;
 #pragma unroll
-      for (int q = 0; q < 6; ++q) g[q][k] = 0.0;
+      for (int q = 0; q < 6; ++q) g[q][k] = (TC)0;
     }
   }
 
-  double *S1 = s1 + el * C::TILE;
-  double *S2 = s2 + el * C::TILE;
+  TC uc[N1];  // contraction input (rounded to bfloat16 in that mode)
 #pragma unroll
-  for (int k = 0; k < N1; ++k) S1[k * C::PLANE + j * C::P + i] = uk[k];
+  for (int k = 0; k < N1; ++k) uc[k] = contraction_input<P>(uk[k]);
+
+  const int slot = el < EPB ? el : 0;  // idle threads alias slot 0 but never write
+  TC *S1 = s1 + slot * T::TILE;
+  TC *S2 = s2 + slot * T::TILE;
+  if (el < EPB) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) S1[k * T::PLANE + j * T::P + i] = uc[k];
+  }
   __syncthreads();
 
-  double Da[N1], Db[N1];
+  TC Da[N1], Db[N1];
 #pragma unroll
   for (int l = 0; l < N1; ++l) {
     Da[l] = sD[i * N1 + l];
     Db[l] = sD[j * N1 + l];
   }
-  double wr[N1], ws[N1], wt[N1];
+  TC wr[N1], ws[N1], wt[N1];
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
-    double ur = 0.0, us = 0.0, ut = 0.0;
+    TC ur = 0, us = 0, ut = 0;
 #pragma unroll
     for (int l = 0; l < N1; ++l) {
-      ur += Da[l] * S1[k * C::PLANE + j * C::P + l];
-      us += Db[l] * S1[k * C::PLANE + l * C::P + i];
-      ut += sD[k * N1 + l] * uk[l];
+      ur += Da[l] * S1[k * T::PLANE + j * T::P + l];
+      us += Db[l] * S1[k * T::PLANE + l * T::P + i];
+      ut += sD[k * N1 + l] * uc[l];
     }
-    wr[k] = g[0][k] * ur + g[1][k] * us + g[2][k] * ut;
-    ws[k] = g[1][k] * ur + g[3][k] * us + g[4][k] * ut;
-    wt[k] = g[2][k] * ur + g[4][k] * us + g[5][k] * ut;
+    wr[k] = contraction_input<P>(g[0][k] * ur + g[1][k] * us + g[2][k] * ut);
+    ws[k] = contraction_input<P>(g[1][k] * ur + g[3][k] * us + g[4][k] * ut);
+    wt[k] = contraction_input<P>(g[2][k] * ur + g[4][k] * us + g[5][k] * ut);
   }
   __syncthreads();
+  if (el < EPB) {
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    S1[k * C::PLANE + j * C::P + i] = wr[k];
-    S2[k * C::PLANE + j * C::P + i] = ws[k];
+    for (int k = 0; k < N1; ++k) {
+      S1[k * T::PLANE + j * T::P + i] = wr[k];
+      S2[k * T::PLANE + j * T::P + i] = ws[k];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -125,20 +148,66 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
-    double v = 0.0;
+    TC v = 0;
 #pragma unroll
     for (int l = 0; l < N1; ++l) {
-      v += Da[l] * S1[k * C::PLANE + j * C::P + l];
-      v += Db[l] * S2[k * C::PLANE + l * C::P + i];
+      v += Da[l] * S1[k * T::PLANE + j * T::P + l];
+      v += Db[l] * S2[k * T::PLANE + l * T::P + i];
       v += sD[l * N1 + k] * wt[l];
     }
-    if (active) w[base + k * PL] = v;
-    acc += uk[k] * v;
+    if (active) w[base + k * PL] = (TV)v;
+    acc += (double)uk[k] * (double)v;
   }
   if (CG) {
-    __syncthreads();  // s1 is reused as the reduction buffer
-    const double tot = block_sum_any<C::THREADS>(acc, s1);
-    if (tid == 0) part[blockIdx.x] = tot;
+    // per-element sum of p.(A_L p): fixed tree over the element's threads
+    sred[tid] = acc;
+    __syncthreads();
+    constexpr int P2 = next_pow2(PL);
+    const int lt = ij;
+#pragma unroll
+    for (int s = P2 / 2; s > 0; s >>= 1) {
+      if (el < EPB && lt < s && lt + s < PL) sred[tid] += sred[tid + s];
+      __syncthreads();
+    }
+    if (active && lt == 0) part_el[e] = sred[tid];
+  }
+  __syncthreads();  // LDS is free for the next tile
+}
+
+namespace {
+
+template <int N1, class P, bool CG>
+__global__ void __launch_bounds__(AxCfg<N1>::THREADS)
+    ax_kernel(int64_t E, const typename P::TC *__restrict__ Dg, const typename P::TG *__restrict__ G,
+              typename P::TV *u, typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,
+              const typename P::TV *__restrict__ minv, typename P::TV *__restrict__ x,
+              CgState *__restrict__ st, double *__restrict__ part) {
+  using C = AxCfg<N1>;
+  using TC = typename P::TC;
+  __shared__ TC sD[N1 * N1];
+  __shared__ TC s1[C::EPB * AxTile<N1>::TILE];
+  __shared__ TC s2[C::EPB * AxTile<N1>::TILE];
+  __shared__ double sred[CG ? C::THREADS : 1];
+  double alpha = 0.0, beta = 0.0;
+  if (CG) {
+    if (st->done) return;  // uniform: converged solves skip all work
+    alpha = st->alpha;
+    beta = st->beta;
+  }
+  ax_tile<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha, beta,
+                             part, sD, s1, s2, sred);
+}
+
+// Rounded copy of G for a low-precision operator.
+template <class P>
+__global__ void __launch_bounds__(256)
+    convert_g_kernel(int64_t n, const double *__restrict__ src, typename P::TG *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if constexpr (P::kBf16) {
+    dst[i] = bf16_bits((float)src[i]);
+  } else {
+    dst[i] = (typename P::TG)src[i];
   }
 }
 
@@ -151,11 +220,12 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
                       const double *__restrict__ nodes, double *__restrict__ G,
                       double *__restrict__ diag) {
   using C = AxCfg<N1>;
-  constexpr int NP = C::NP;
+  using T = AxTile<N1>;
+  constexpr int NP = T::NP;
   constexpr int PL = N1 * N1;
   constexpr int N = N1 - 1;
   __shared__ double sD[N1 * N1];
-  __shared__ double sx[3][C::EPB * C::TILE];
+  __shared__ double sx[3][C::EPB * T::TILE];
 
   const int tid = threadIdx.x;
   const int el = tid / PL;
@@ -173,15 +243,15 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   const double xi_i = nodes[i], xi_j = nodes[j];
   const double X0 = (ex + 0.5 * (xi_i + 1.0)) / b.nx;
   const double Y0 = (ey + 0.5 * (xi_j + 1.0)) / b.ny;
-  double *SX = sx[0] + el * C::TILE;
-  double *SY = sx[1] + el * C::TILE;
-  double *SZ = sx[2] + el * C::TILE;
+  double *SX = sx[0] + el * T::TILE;
+  double *SY = sx[1] + el * T::TILE;
+  double *SZ = sx[2] + el * T::TILE;
   const double twopi = 2.0 * M_PI;
   for (int k = 0; k < N1; ++k) {
     const double Z0 = (ez + 0.5 * (nodes[k] + 1.0)) / b.nz;
     double bump = 0.0;
     if (amp != 0.0) bump = amp * sin(twopi * X0) * sin(twopi * Y0) * sin(twopi * Z0);
-    const int o = k * C::PLANE + j * C::P + i;
+    const int o = k * T::PLANE + j * T::P + i;
     SX[o] = X0 + bump;
     SY[o] = Y0 + bump;
     SZ[o] = Z0 + bump;
@@ -197,9 +267,9 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
     for (int d = 0; d < 3; ++d) {
       double a = 0.0, bb = 0.0, c = 0.0;
       for (int l = 0; l < N1; ++l) {
-        a += sD[i * N1 + l] * S[d][k * C::PLANE + j * C::P + l];
-        bb += sD[j * N1 + l] * S[d][k * C::PLANE + l * C::P + i];
-        c += sD[k * N1 + l] * S[d][l * C::PLANE + j * C::P + i];
+        a += sD[i * N1 + l] * S[d][k * T::PLANE + j * T::P + l];
+        bb += sD[j * N1 + l] * S[d][k * T::PLANE + l * T::P + i];
+        c += sD[k * N1 + l] * S[d][l * T::PLANE + j * T::P + i];
       }
       J[d][0] = a;
       J[d][1] = bb;
@@ -240,7 +310,7 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   }
   __syncthreads();
   for (int k = 0; k < N1; ++k) {
-    const int o = k * C::PLANE + j * C::P + i;
+    const int o = k * T::PLANE + j * T::P + i;
     SX[o] = grr[k];
     SY[o] = gss[k];
     SZ[o] = gtt[k];
@@ -251,9 +321,9 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
     double d = 0.0;
     for (int l = 0; l < N1; ++l) {
       const double a = sD[l * N1 + i], bb = sD[l * N1 + j], c = sD[l * N1 + k];
-      d += a * a * SX[k * C::PLANE + j * C::P + l];
-      d += bb * bb * SY[k * C::PLANE + l * C::P + i];
-      d += c * c * SZ[l * C::PLANE + j * C::P + i];
+      d += a * a * SX[k * T::PLANE + j * T::P + l];
+      d += bb * bb * SY[k * T::PLANE + l * T::P + i];
+      d += c * c * SZ[l * T::PLANE + j * T::P + i];
     }
     const double Dkk = sD[k * N1 + k];
     d += 2.0 * Dii * Djj * grs[k] + 2.0 * Dii * Dkk * grt[k] + 2.0 * Djj * Dkk * gst[k];
@@ -262,19 +332,23 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   (void)N;
 }
 
-template <int N1>
-hipError_t ax_dispatch(const Box &b, const double *D, const double *G, double *u, double *w,
-                       const double *r, const double *minv, double *x, CgState *cg, double *part,
-                       hipStream_t s) {
+template <int N1, class P>
+hipError_t ax_dispatch(const Box &b, const void *D, const void *G, void *u, void *w, const void *r,
+                       const void *minv, void *x, CgState *cg, double *part, hipStream_t s) {
   using C = AxCfg<N1>;
+  using TV = typename P::TV;
+  using TG = typename P::TG;
+  using TC = typename P::TC;
   const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
   if (blocks == 0) return hipSuccess;
   if (cg)
-    hipLaunchKernelGGL((ax_f64_kernel<N1, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
-                       b.E(), D, G, u, w, r, minv, x, cg, part);
+    hipLaunchKernelGGL((ax_kernel<N1, P, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
+                       (const TV *)minv, (TV *)x, cg, part);
   else
-    hipLaunchKernelGGL((ax_f64_kernel<N1, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
-                       s, b.E(), D, G, u, w, r, minv, x, cg, part);
+    hipLaunchKernelGGL((ax_kernel<N1, P, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
+                       (const TV *)minv, (TV *)x, cg, part);
   return hipGetLastError();
 }
 
@@ -317,12 +391,53 @@ hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double 
   switch (b.N) {
 #define CASE(n) \
   case n:       \
-    return ax_dispatch<n + 1>(b, D, G, u, w, r, minv, x, cg, part, s);
+    return ax_dispatch<n + 1, PrecF64>(b, D, G, u, w, r, minv, x, cg, part, s);
     SEM_FOR_EACH_ORDER(CASE)
 #undef CASE
     default:
       return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_ax_lowp(const Box &b, int prec, const float *D, const void *G, float *u, float *w,
+                          const float *r, const float *minv, float *x, CgState *cg, double *part,
+                          hipStream_t s) {
+  if (prec == SEM_F32) {
+    switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return ax_dispatch<n + 1, PrecF32>(b, D, G, u, w, r, minv, x, cg, part, s);
+      SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  if (prec == SEM_BF16) {
+    switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return ax_dispatch<n + 1, PrecBF16>(b, D, G, u, w, r, minv, x, cg, part, s);
+      SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_convert_g(int prec, int64_t n, const double *src, void *dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (prec == SEM_F32)
+    hipLaunchKernelGGL(convert_g_kernel<PrecF32>, dim3(blocks), dim3(256), 0, s, n, src, (float *)dst);
+  else if (prec == SEM_BF16)
+    hipLaunchKernelGGL(convert_g_kernel<PrecBF16>, dim3(blocks), dim3(256), 0, s, n, src,
+                       (uint16_t *)dst);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_setup_geom(const Box &b, double amp, const double *D, const double *nodes,

@@ -9,6 +9,62 @@
 
 namespace semk {
 
+// ---------------------------------------------------------------- precisions
+// Storage and arithmetic of one operator variant: vectors TV, geometric
+// factors TG, contractions in TC.  BF16 keeps G as bfloat16 bits and rounds
+// both contraction inputs (u and the G-weighted gradient) to bfloat16, so
+// every product is exact in FP32 and only the FP32 accumulation rounds.
+struct PrecF64 {
+  using TV = double;
+  using TG = double;
+  using TC = double;
+  static constexpr bool kBf16 = false;
+};
+struct PrecF32 {
+  using TV = float;
+  using TG = float;
+  using TC = float;
+  static constexpr bool kBf16 = false;
+};
+struct PrecBF16 {
+  using TV = float;
+  using TG = uint16_t;
+  using TC = float;
+  static constexpr bool kBf16 = true;
+};
+
+// Round an FP32 value to the nearest bfloat16 (ties to even); finite inputs.
+__host__ __device__ inline uint16_t bf16_bits(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+__device__ inline float round_bf16(float f) { return bf16_value(bf16_bits(f)); }
+
+template <class P>
+__device__ inline typename P::TC load_g(const typename P::TG *p) {
+  if constexpr (P::kBf16) {
+    return bf16_value(*p);
+  } else {
+    return (typename P::TC)(*p);
+  }
+}
+template <class P>
+__device__ inline typename P::TC contraction_input(typename P::TC v) {
+  if constexpr (P::kBf16) {
+    return round_bf16(v);
+  } else {
+    return v;
+  }
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

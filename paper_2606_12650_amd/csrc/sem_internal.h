@@ -97,14 +97,24 @@ hipError_t launch_fill_c(const Box &b, double *c, hipStream_t s);
 
 // w = A_L u.  With cg != null (a CG iteration) a prologue first finishes the
 // previous iteration, x += alpha p, then forms p <- Minv r + beta p (u is p,
-// updated in place), and per-block partial sums of p.w go to part
-// (ax_num_blocks of them).
+// updated in place), and the per-element sums of p.w go to part (E of them).
 hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
                          const double *r, const double *minv, double *x, CgState *cg,
                          double *part, hipStream_t s);
 
+// Low-precision operator (prec SEM_F32 or SEM_BF16): FP32 vectors, G stored
+// as float or bfloat16 bits, D as float (bfloat16-rounded in BF16 mode),
+// FP32 accumulation; the CG variant mirrors launch_ax_f64 (x is the inner
+// correction e).
+hipError_t launch_ax_lowp(const Box &b, int prec, const float *D, const void *G, float *u, float *w,
+                          const float *r, const float *minv, float *x, CgState *cg, double *part,
+                          hipStream_t s);
+// dst[i] = src[i] rounded to float (SEM_F32) or to bfloat16 bits (SEM_BF16).
+hipError_t launch_convert_g(int prec, int64_t n, const double *src, void *dst, hipStream_t s);
+
 // out = the copies of every node of wl summed (GatherMode); wl != out.
 hipError_t launch_gather(const Box &b, const double *wl, double *out, int mode, hipStream_t s);
+hipError_t launch_gather_f32(const Box &b, const float *wl, float *out, int mode, hipStream_t s);
 
 // CG start: x = 0, r = mask o b, p = 0, partials of <r, Minv r>_c and
 // ||b||_c^2; then a one-group launch sets rho, ||b||_c and the tolerance.
@@ -118,6 +128,25 @@ hipError_t launch_cg_update(const Box &b, double *r, const double *w, const doub
 // After the last iteration: x += alpha p if that iteration's update ran.
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
                             hipStream_t s);
+// FP32 versions for the inner solver of the inner-outer CG.
+hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
+                                CgState *st, double *part_rr, double *part_rz, hipStream_t s);
+hipError_t launch_cg_finish_f32(const Box &b, float *x, const float *p, const CgState *st,
+                                hipStream_t s);
+
+// Inner-outer CG steps.  inner_start: reset the inner state (tolerance
+// rtol2 = eta^2, iteration cap), r_in = r / ||r||_c in FP32, e = p = 0, and
+// rho, ||r_in||_c of the inner state.  outer_update: x += ||r||_c e.
+// outer_step (after w64 = A_L x): r = mask o (b - QQ^T w64), ||r||_c^2, the
+// outer count and the done flag of the outer state.
+hipError_t launch_inner_start(const Box &b, const double *r64, CgState *outer, CgState *inner,
+                              double rtol2, int max_iter, float *rin, float *e, float *p,
+                              const float *minv32, double *part_a, double *part_b, hipStream_t s);
+hipError_t launch_outer_update(const Box &b, double *x, const float *e, const CgState *outer,
+                               hipStream_t s);
+hipError_t launch_outer_step(const Box &b, double *x, const float *e, const double *bvec,
+                             const double *w64, double *r64, CgState *outer, double *part,
+                             hipStream_t s);
 // One-group launches that finish the reductions and advance the scalars:
 // alpha = rho / <p, A p> (breakdown check), and after the update
 // iteration count, ||r||_c, rho, beta and the done flag.

@@ -21,10 +21,9 @@ namespace semk {
 namespace {
 
 // ------------------------------------------------------------ gather-scatter
-template <int N1, int MODE>
+template <int N1, int MODE, typename T>
 __global__ void __launch_bounds__(kVecThreads)
-    gather_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ wl,
-                  double *__restrict__ out) {
+    gather_kernel(Box b, int64_t L, int64_t ntiles, const T *__restrict__ wl, T *__restrict__ out) {
   const int64_t tile = xcd_tile(ntiles);
   if (tile >= ntiles) return;
   const int64_t base = tile * kVecTile + threadIdx.x;
@@ -40,7 +39,7 @@ __global__ void __launch_bounds__(kVecThreads)
         v = gather_copies<N1>(wl, b, n, idx);
         if (MODE == kGatherInverse) v = 1.0 / v;
       }
-      out[idx] = v;
+      out[idx] = (T)v;
     }
   }
 }
@@ -101,10 +100,10 @@ __global__ void __launch_bounds__(kFinThreads)
   }
 }
 
-template <int N1>
+template <int N1, typename TV>
 __global__ void __launch_bounds__(kVecThreads)
-    cg_update_kernel(Box b, int64_t L, int64_t ntiles, double *__restrict__ r,
-                     const double *__restrict__ w, const double *__restrict__ minv,
+    cg_update_kernel(Box b, int64_t L, int64_t ntiles, TV *__restrict__ r,
+                     const TV *__restrict__ w, const TV *__restrict__ minv,
                      CgState *__restrict__ st, double *__restrict__ part_rr,
                      double *__restrict__ part_rz) {
   __shared__ double sred[kVecThreads / 64];
@@ -121,11 +120,12 @@ __global__ void __launch_bounds__(kVecThreads)
         const Node<N1> n = node_at<N1>(b, idx);
         if (!n.boundary) {
           const double wa = gather_copies<N1>(w, b, n, idx);
-          const double rv = r[idx] - alpha * wa;
-          r[idx] = rv;
+          const TV rt = (TV)((double)r[idx] - alpha * wa);
+          r[idx] = rt;
+          const double rv = (double)rt;
           const double c = 1.0 / (double)n.mult;
           rr += c * rv * rv;
-          rz += c * rv * (minv[idx] * rv);
+          rz += c * rv * ((double)minv[idx] * rv);
         }
       }
     }
@@ -183,19 +183,138 @@ __global__ void __launch_bounds__(kFinThreads)
   }
 }
 
+// Outer step of the inner-outer solve: ||r||_c^2 of the true residual, the
+// outer count and the done flag.
+__global__ void __launch_bounds__(kFinThreads)
+    outer_finish_kernel(CgState *st, const double *__restrict__ part, int64_t n) {
+  __shared__ double sred[kFinThreads / 64];
+  const int done = st->done;
+  const int it = st->iter + 1;
+  const int max_iter = st->max_iter;
+  const double tol2 = st->tol2;
+  const double rr = sum_partials<kFinThreads>(part, n, sred);
+  if (threadIdx.x == 0 && done == kRunning) {
+    st->iter = it;
+    st->rnorm2 = rr;
+    if (!isfinite(rr)) {
+      st->done = kBreakdown;
+    } else if (rr <= tol2) {
+      st->done = kConverged;
+    } else if (it >= max_iter) {
+      st->done = kMaxIter;
+    }
+  }
+}
+
 // The last x += alpha p of a solve (the operator kernel folds it into the
 // next iteration's prologue, and there is no next iteration).
+template <typename TV>
 __global__ void __launch_bounds__(kVecThreads)
-    cg_finish_kernel(int64_t L, double *__restrict__ x, const double *__restrict__ p,
+    cg_finish_kernel(int64_t L, TV *__restrict__ x, const TV *__restrict__ p,
                      const CgState *__restrict__ st) {
   if (st->done == kRunning || st->done_stage != 2) return;
-  const double alpha = st->alpha;
+  const TV alpha = (TV)st->alpha;
   const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kVecItems; ++u) {
     const int64_t idx = base + (int64_t)u * kVecThreads;
     if (idx < L) x[idx] += alpha * p[idx];
   }
+}
+
+// ------------------------------------------------------------ inner-outer CG
+// Reset the inner solver's state for a new outer step.
+__global__ void inner_reset_kernel(CgState *st, double rtol2, int max_iter) {
+  if (threadIdx.x == 0) {
+    st->done = kRunning;
+    st->iter = 0;
+    st->done_stage = 0;
+    st->max_iter = max_iter;
+    st->rtol2 = rtol2;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+  }
+}
+
+// Inner start: r_in = r / ||r||_c in FP32, e = 0, p = 0, partials of
+// <r_in, Minv r_in>_c and ||r_in||_c^2 (FP64 accumulation).
+template <int N1>
+__global__ void __launch_bounds__(kVecThreads)
+    inner_start_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ r64,
+                       const CgState *__restrict__ outer, float *__restrict__ rin,
+                       float *__restrict__ e, float *__restrict__ p,
+                       const float *__restrict__ minv32, double *__restrict__ part_rz,
+                       double *__restrict__ part_rr) {
+  __shared__ double sred[kVecThreads / 64];
+  const double inv_s = 1.0 / sqrt(outer->rnorm2);
+  const int64_t tile = xcd_tile(ntiles);
+  double rz = 0.0, rr = 0.0;
+  if (tile < ntiles) {
+    const int64_t base = tile * kVecTile + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+      const int64_t idx = base + (int64_t)u * kVecThreads;
+      if (idx < L) {
+        const Node<N1> n = node_at<N1>(b, idx);
+        const float rv = (float)(r64[idx] * inv_s);
+        rin[idx] = rv;
+        e[idx] = 0.0f;
+        p[idx] = 0.0f;
+        const double c = 1.0 / (double)n.mult;
+        rz += c * (double)rv * ((double)minv32[idx] * (double)rv);
+        rr += c * (double)rv * (double)rv;
+      }
+    }
+  }
+  const double a = block_sum<kVecThreads>(rz, sred);
+  const double c = block_sum<kVecThreads>(rr, sred);
+  if (threadIdx.x == 0) {
+    part_rz[tile] = a;
+    part_rr[tile] = c;
+  }
+}
+
+// x += ||r||_c e (the scaled inner correction), in FP64.
+__global__ void __launch_bounds__(kVecThreads)
+    outer_update_kernel(int64_t L, double *__restrict__ x, const float *__restrict__ e,
+                        const CgState *__restrict__ outer) {
+  if (outer->done != kRunning) return;
+  const double s = sqrt(outer->rnorm2);
+  const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kVecItems; ++u) {
+    const int64_t idx = base + (int64_t)u * kVecThreads;
+    if (idx < L) x[idx] += s * (double)e[idx];
+  }
+}
+
+// True residual r = mask o (b - QQ^T w_L) with w_L = A_L x (FP64) and the
+// partials of ||r||_c^2.
+template <int N1>
+__global__ void __launch_bounds__(kVecThreads)
+    residual_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ bvec,
+                    const double *__restrict__ wl, double *__restrict__ r,
+                    const CgState *__restrict__ outer, double *__restrict__ part) {
+  __shared__ double sred[kVecThreads / 64];
+  const int done = outer->done;
+  const int64_t tile = xcd_tile(ntiles);
+  double rr = 0.0;
+  if (tile < ntiles && done == kRunning) {
+    const int64_t base = tile * kVecTile + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+      const int64_t idx = base + (int64_t)u * kVecThreads;
+      if (idx < L) {
+        const Node<N1> n = node_at<N1>(b, idx);
+        double rv = 0.0;
+        if (!n.boundary) rv = bvec[idx] - gather_copies<N1>(wl, b, n, idx);
+        r[idx] = rv;
+        rr += rv * rv / (double)n.mult;
+      }
+    }
+  }
+  const double a = block_sum<kVecThreads>(rr, sred);
+  if (threadIdx.x == 0) part[tile] = a;
 }
 
 // ------------------------------------------------------------ setup helpers
@@ -286,27 +405,53 @@ inline dim3 xcd_vec_grid(int64_t n) { return dim3((unsigned)vec_grid_blocks(n));
     default: return hipErrorInvalidValue;                               \
   }
 
-hipError_t launch_gather(const Box &b, const double *wl, double *out, int mode, hipStream_t s) {
+#define DISPATCH_N_MODE_T(b, MODE, T, KERNEL, ...)                        \
+  switch ((b).N) {                                                        \
+    case 1: hipLaunchKernelGGL((KERNEL<2, MODE, T>), __VA_ARGS__); break;   \
+    case 2: hipLaunchKernelGGL((KERNEL<3, MODE, T>), __VA_ARGS__); break;   \
+    case 3: hipLaunchKernelGGL((KERNEL<4, MODE, T>), __VA_ARGS__); break;   \
+    case 4: hipLaunchKernelGGL((KERNEL<5, MODE, T>), __VA_ARGS__); break;   \
+    case 5: hipLaunchKernelGGL((KERNEL<6, MODE, T>), __VA_ARGS__); break;   \
+    case 6: hipLaunchKernelGGL((KERNEL<7, MODE, T>), __VA_ARGS__); break;   \
+    case 7: hipLaunchKernelGGL((KERNEL<8, MODE, T>), __VA_ARGS__); break;   \
+    case 8: hipLaunchKernelGGL((KERNEL<9, MODE, T>), __VA_ARGS__); break;   \
+    case 9: hipLaunchKernelGGL((KERNEL<10, MODE, T>), __VA_ARGS__); break;  \
+    case 10: hipLaunchKernelGGL((KERNEL<11, MODE, T>), __VA_ARGS__); break; \
+    case 11: hipLaunchKernelGGL((KERNEL<12, MODE, T>), __VA_ARGS__); break; \
+    case 12: hipLaunchKernelGGL((KERNEL<13, MODE, T>), __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                 \
+  }
+
+template <typename T>
+hipError_t gather_typed(const Box &b, const T *wl, T *out, int mode, hipStream_t s) {
   const int64_t L = b.L();
   if (L == 0) return hipSuccess;
   const int64_t nt = vec_num_blocks(L);
   switch (mode) {
     case kGatherAssembled:
-      DISPATCH_N_MODE(b, kGatherAssembled, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s,
-                      b, L, nt, wl, out);
+      DISPATCH_N_MODE_T(b, kGatherAssembled, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0,
+                        s, b, L, nt, wl, out);
       break;
     case kGatherMasked:
-      DISPATCH_N_MODE(b, kGatherMasked, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b,
-                      L, nt, wl, out);
+      DISPATCH_N_MODE_T(b, kGatherMasked, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s,
+                        b, L, nt, wl, out);
       break;
     case kGatherInverse:
-      DISPATCH_N_MODE(b, kGatherInverse, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s,
-                      b, L, nt, wl, out);
+      DISPATCH_N_MODE_T(b, kGatherInverse, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0,
+                        s, b, L, nt, wl, out);
       break;
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_gather(const Box &b, const double *wl, double *out, int mode, hipStream_t s) {
+  return gather_typed<double>(b, wl, out, mode, s);
+}
+
+hipError_t launch_gather_f32(const Box &b, const float *wl, float *out, int mode, hipStream_t s) {
+  return gather_typed<float>(b, wl, out, mode, s);
 }
 
 hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r, double *p,
@@ -338,15 +483,71 @@ hipError_t launch_cg_update(const Box &b, double *r, const double *w, const doub
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
   const int64_t L = b.L();
   const int64_t nt = vec_num_blocks(L);
-  DISPATCH_N(b, cg_update_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, r, w, minv,
-             st, part_rr, part_rz);
+  DISPATCH_N_MODE(b, double, cg_update_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt,
+                  r, w, minv, st, part_rr, part_rz);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
+                                CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
+  const int64_t L = b.L();
+  const int64_t nt = vec_num_blocks(L);
+  DISPATCH_N_MODE(b, float, cg_update_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt,
+                  r, w, minv, st, part_rr, part_rz);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
                             hipStream_t s) {
   const int64_t L = b.L();
-  hipLaunchKernelGGL(cg_finish_kernel, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
+  hipLaunchKernelGGL(cg_finish_kernel<double>, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish_f32(const Box &b, float *x, const float *p, const CgState *st,
+                                hipStream_t s) {
+  const int64_t L = b.L();
+  hipLaunchKernelGGL(cg_finish_kernel<float>, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_start(const Box &b, const double *r64, CgState *outer, CgState *inner,
+                              double rtol2, int max_iter, float *rin, float *e, float *p,
+                              const float *minv32, double *part_a, double *part_b, hipStream_t s) {
+  const int64_t L = b.L();
+  const int64_t nt = vec_num_blocks(L);
+  hipLaunchKernelGGL(inner_reset_kernel, dim3(1), dim3(64), 0, s, inner, rtol2, max_iter);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  DISPATCH_N(b, inner_start_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, r64, outer,
+             rin, e, p, minv32, part_a, part_b);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, inner, part_a, part_b,
+                     vec_grid_blocks(L));
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_step(const Box &b, double *x, const float *e, const double *bvec,
+                             const double *w64, double *r64, CgState *outer, double *part,
+                             hipStream_t s) {
+  const int64_t L = b.L();
+  const int64_t nt = vec_num_blocks(L);
+  DISPATCH_N(b, residual_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, bvec, w64, r64,
+             outer, part);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(outer_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, outer, part,
+                     vec_grid_blocks(L));
+  (void)x;
+  (void)e;
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_update(const Box &b, double *x, const float *e, const CgState *outer,
+                               hipStream_t s) {
+  const int64_t L = b.L();
+  hipLaunchKernelGGL(outer_update_kernel, vec_grid(L), dim3(kVecThreads), 0, s, L, x, e, outer);
   return hipGetLastError();
 }
 

@@ -105,6 +105,17 @@ class SemOperator:
         L.check("sem_ax", L.lib().sem_ax(self._ctx, _ptr(u), _ptr(w), int(mode), _stream(self.device)))
         return w
 
+    def ax_lowp(self, u: torch.Tensor, mode: int = MASKED, out: torch.Tensor | None = None) -> torch.Tensor:
+        """``sem_ax_lowp``: the low-precision operator on FP32 vectors."""
+        if u.dtype != torch.float32 or not u.is_cuda or not u.is_contiguous() or u.numel() != self.L:
+            raise ValueError("u must be a contiguous float32 CUDA tensor with L entries")
+        w = torch.empty(self.L, dtype=torch.float32, device=self.device) if out is None else out
+        if w.dtype != torch.float32 or w.numel() != self.L or not w.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor with L entries")
+        L.check("sem_ax_lowp", L.lib().sem_ax_lowp(self._ctx, _ptr(u), _ptr(w), int(mode),
+                                                   _stream(self.device)))
+        return w
+
     def cg(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8,
            max_iter: int = 0, fixed_iter: int = 0, check_every: int = 0, mixed: bool = False,
            inner_rtol: float = 0.0, inner_max: int = 0, raise_on_fail: bool = True):
