@@ -168,6 +168,56 @@ int vec_dot(int64_t n, const double *x_dev, const double *y_dev, const double *w
  * listed with the field. */
 int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent solves (different meshes, orders 1..11, FP64 or mixed
+ * precision) advance together: each batched step runs one CG iteration of
+ * every active solve in seven launches (persistent kernels over work lists of
+ * (solve, element tile) and (solve, vector tile) items, plus one work-group
+ * per solve for the scalars).  Every solve's arithmetic and reduction order
+ * are those of sem_cg, so an FP64 solve gives the same bits in a batch as
+ * alone.  Solves join and leave between steps (continuous batching); the
+ * step's captured graph does not change when they do.  The batch holds no
+ * memory of its own on the device beyond its workspace; each solve keeps its
+ * state in its sem_ctx workspace.  Calls on one batch must not overlap. */
+typedef struct sem_batch sem_batch;
+
+/* Workspace of a batch: slot table, work lists (capacities in items: one
+ * operator item per tile of elements, one vector item per 2048 entries of a
+ * solve's L-vector), status records.  0 for invalid capacities. */
+size_t sem_batch_workspace_bytes(int max_slots, int64_t max_op_items, int64_t max_vec_items);
+
+/* Create a batch in `dev_ws` (256-byte aligned).  Synchronous. */
+int sem_batch_create(int max_slots, int64_t max_op_items, int64_t max_vec_items, void *dev_ws,
+                     size_t ws_bytes, void *stream, sem_batch **out);
+
+/* Elements per operator item for one order (autotuner hook; applies to solves
+ * added afterwards).  SEM_ERR_UNSUPPORTED for a tile that is not compiled. */
+int sem_batch_set_tile(sem_batch *batch, int order, int elements_per_item);
+
+/* Start the solve of A x = b on ctx (tolerance mode, opts as for sem_cg;
+ * opts->mixed needs ctx's low-precision copy) in a free slot.  b and x must
+ * stay valid until the slot is removed; x holds the solution once the slot
+ * reports finished.  The context cannot run sem_cg or join another batch
+ * until it is removed.  Synchronous.  *slot receives the slot index. */
+int sem_batch_add(sem_batch *batch, sem_ctx *ctx, const double *b_dev, double *x_dev,
+                  const sem_cg_opts *opts, int *slot, void *stream);
+
+/* Run `iters` batched iterations (asynchronous; captured as a graph on a
+ * non-null stream).  Finished solves cost nothing. */
+int sem_batch_step(sem_batch *batch, int iters, void *stream);
+
+/* Blocking status read: up to `cap` finished slots and their results into
+ * finished[] / infos[] (*n_finished of them), and the number of occupied slots
+ * into *n_active (may be NULL).  Finished slots stay until removed. */
+int sem_batch_poll(sem_batch *batch, int *finished, int cap, int *n_finished, sem_cg_info *infos,
+                   int *n_active, void *stream);
+
+/* Free a slot (finished or not) and release its context.  Synchronous. */
+int sem_batch_remove(sem_batch *batch, int slot, void *stream);
+
+/* Free the host handle (the workspace stays the caller's). */
+int sem_batch_destroy(sem_batch *batch);
+
 /* Thread-local text of the last error ("" if none). */
 const char *sem_last_error(void);
 

@@ -27,7 +27,8 @@ SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2
 EXPORTS = (
     "sem_workspace_bytes", "sem_setup", "sem_destroy", "sem_nlocal", "sem_ax", "sem_cg",
     "vec_axpy", "vec_dot_workspace_bytes", "vec_dot", "sem_export", "sem_last_error",
-    "sem_ax_lowp",
+    "sem_ax_lowp", "sem_batch_workspace_bytes", "sem_batch_create", "sem_batch_set_tile",
+    "sem_batch_add", "sem_batch_step", "sem_batch_poll", "sem_batch_remove", "sem_batch_destroy",
 )
 
 
@@ -75,6 +76,15 @@ def _declare(lib):
         "vec_dot": (ctypes.c_int, [i64, vp, vp, vp, vp, vp, sz, vp]),
         "sem_export": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),
         "sem_last_error": (ctypes.c_char_p, []),
+        "sem_batch_workspace_bytes": (sz, [ctypes.c_int, i64, i64]),
+        "sem_batch_create": (ctypes.c_int, [ctypes.c_int, i64, i64, vp, sz, vp, P(vp)]),
+        "sem_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "sem_batch_add": (ctypes.c_int, [vp, vp, vp, vp, P(SemCgOpts), P(ctypes.c_int), vp]),
+        "sem_batch_step": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "sem_batch_poll": (ctypes.c_int, [vp, P(ctypes.c_int), ctypes.c_int, P(ctypes.c_int),
+                                          P(SemCgInfo), P(ctypes.c_int), vp]),
+        "sem_batch_remove": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "sem_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -187,6 +187,7 @@ struct sem_ctx {
   int64_t n_ax_blocks, n_vec_blocks;  // partial counts: elements, streaming tiles
   CgState host_state;  // staging for the state upload / status reads
   CgState host_inner;
+  int in_batch;  // 1 while the context is a slot of a batch
   // cached graphs: [0] FP64 CG iterations into graph_x, [1] inner iterations
   hipGraphExec_t graph[2];
   hipStream_t graph_stream[2];
@@ -334,6 +335,7 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->st = (CgState *)(c->ws + lay.state);
   c->n_ax_blocks = c->box.E();
   c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
+  c->in_batch = 0;
   for (int slot = 0; slot < 2; ++slot) {
     c->graph[slot] = nullptr;
     c->graph_stream[slot] = nullptr;
@@ -392,6 +394,7 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
 
 int sem_destroy(sem_ctx *ctx) {
   if (!ctx) return fail(SEM_ERR_ARG, "sem_destroy: null handle");
+  if (ctx->in_batch) return fail(SEM_ERR_ARG, "sem_destroy: remove the context from its batch first");
   drop_graph(ctx, 0);
   drop_graph(ctx, 1);
   delete ctx;
@@ -424,6 +427,7 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
            void *stream) {
   if (!ctx) return fail(SEM_ERR_ARG, "sem_cg: null handle");
   if (!b || !x || !opts || !info) return fail(SEM_ERR_ARG, "sem_cg: null argument");
+  if (ctx->in_batch) return fail(SEM_ERR_ARG, "sem_cg: the context is a slot of a batch");
   if (b == x) return fail(SEM_ERR_ARG, "sem_cg: b and x must differ");
   if (opts->mixed && ctx->desc.lowprec == SEM_F64)
     return fail(SEM_ERR_ARG, "sem_cg: mixed precision needs a mesh set up with lowprec SEM_F32 or SEM_BF16");
@@ -472,11 +476,10 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
                               inner_max, s);
       if (rc != SEM_OK) return rc;
       inner_total += hi.iter;
-      SEM_HIP(semk::launch_cg_finish_f32(bx, ctx->e, ctx->pin, ctx->st_in, s));
-      SEM_HIP(semk::launch_outer_update(bx, x, ctx->e, ctx->st, s));
+      SEM_HIP(semk::launch_outer_correct(bx, x, ctx->e, ctx->pin, ctx->st_in, ctx->st, s));
       SEM_HIP(semk::launch_ax_f64(bx, ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
                                   nullptr, s));
-      SEM_HIP(semk::launch_outer_step(bx, x, ctx->e, b, ctx->w, ctx->r, ctx->st, ctx->part_rr, s));
+      SEM_HIP(semk::launch_outer_step(bx, b, ctx->w, ctx->r, ctx->st, ctx->part_rr, s));
       SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
       SEM_HIP(hipStreamSynchronize(s));
       if (hi.iter == 0 && h.done == semk::kRunning) {
@@ -564,6 +567,336 @@ int sem_export(sem_ctx *ctx, int field, double *dst, void *stream) {
     default:
       return fail(SEM_ERR_ARG, "sem_export: unknown field");
   }
+  return SEM_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batches
+
+struct sem_batch {
+  int max_slots;
+  int64_t max_op_items, max_vec_items;
+  semk::BatchSlot *d_slots;
+  semk::BatchItem *d_op, *d_vec;
+  int *d_counts;
+  semk::BatchStatus *d_status;
+  std::vector<semk::BatchSlot> slots;  // host copies as uploaded at add/remove
+  std::vector<sem_ctx *> ctx;          // null for a free slot
+  std::vector<semk::BatchStatus> status;
+  std::vector<semk::BatchItem> op_host, vec_host;
+  int counts_host[4];
+  int epb[semk::kMaxOrder + 1];
+  hipGraphExec_t graph;
+  hipStream_t graph_stream;
+  int graph_iters;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t slots, op, vec, counts, status, total;
+};
+
+BatchLayout batch_layout(int max_slots, int64_t max_op, int64_t max_vec) {
+  BatchLayout o;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t off = at;
+    at = align_up(at + bytes);
+    return off;
+  };
+  o.slots = take((size_t)max_slots * sizeof(semk::BatchSlot));
+  o.op = take((size_t)max_op * sizeof(semk::BatchItem));
+  o.vec = take((size_t)max_vec * sizeof(semk::BatchItem));
+  o.counts = take(4 * sizeof(int));
+  o.status = take((size_t)max_slots * sizeof(semk::BatchStatus));
+  o.total = at;
+  return o;
+}
+
+// Rebuild the work lists from the active slots: operator items grouped by
+// order (then slot), streaming items slot by slot.
+int batch_upload_items(sem_batch *B, hipStream_t s) {
+  B->op_host.clear();
+  B->vec_host.clear();
+  for (int order = 1; order <= semk::kMaxOrder; ++order)
+    for (int q = 0; q < B->max_slots; ++q) {
+      if (!B->ctx[q] || B->slots[q].N != order) continue;
+      const semk::BatchSlot &S = B->slots[q];
+      for (int64_t e0 = 0; e0 < S.E; e0 += S.epb) B->op_host.push_back({q, (int)e0});
+    }
+  for (int q = 0; q < B->max_slots; ++q) {
+    if (!B->ctx[q]) continue;
+    const int64_t nt = semk::vec_num_blocks(B->slots[q].L);
+    for (int64_t t = 0; t < nt; ++t) B->vec_host.push_back({q, (int)t});
+  }
+  if ((int64_t)B->op_host.size() > B->max_op_items || (int64_t)B->vec_host.size() > B->max_vec_items)
+    return fail(SEM_ERR_NOMEM, "sem_batch: work lists exceed the batch's item capacity");
+  B->counts_host[0] = (int)B->op_host.size();
+  B->counts_host[1] = (int)B->vec_host.size();
+  B->counts_host[2] = B->counts_host[3] = 0;
+  if (!B->op_host.empty())
+    SEM_HIP(hipMemcpyAsync(B->d_op, B->op_host.data(), B->op_host.size() * sizeof(semk::BatchItem),
+                           hipMemcpyHostToDevice, s));
+  if (!B->vec_host.empty())
+    SEM_HIP(hipMemcpyAsync(B->d_vec, B->vec_host.data(), B->vec_host.size() * sizeof(semk::BatchItem),
+                           hipMemcpyHostToDevice, s));
+  SEM_HIP(hipMemcpyAsync(B->d_counts, B->counts_host, sizeof(B->counts_host), hipMemcpyHostToDevice, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  return SEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sem_batch_workspace_bytes(int max_slots, int64_t max_op_items, int64_t max_vec_items) {
+  if (max_slots < 1 || max_op_items < 1 || max_vec_items < 1) return 0;
+  return batch_layout(max_slots, max_op_items, max_vec_items).total;
+}
+
+int sem_batch_create(int max_slots, int64_t max_op_items, int64_t max_vec_items, void *dev_ws,
+                     size_t ws_bytes, void *stream, sem_batch **out) {
+  if (!out) return fail(SEM_ERR_ARG, "sem_batch_create: null output handle");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 65535 || max_op_items < 1 || max_vec_items < 1 ||
+      max_op_items > INT32_MAX || max_vec_items > INT32_MAX)
+    return fail(SEM_ERR_ARG, "sem_batch_create: capacities out of range");
+  if (!dev_ws || ((uintptr_t)dev_ws) % kAlign != 0)
+    return fail(SEM_ERR_ARG, "sem_batch_create: workspace null or not 256-byte aligned");
+  const BatchLayout lay = batch_layout(max_slots, max_op_items, max_vec_items);
+  if (ws_bytes < lay.total) return fail(SEM_ERR_NOMEM, "sem_batch_create: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  sem_batch *B = new sem_batch();
+  char *ws = (char *)dev_ws;
+  B->max_slots = max_slots;
+  B->max_op_items = max_op_items;
+  B->max_vec_items = max_vec_items;
+  B->d_slots = (semk::BatchSlot *)(ws + lay.slots);
+  B->d_op = (semk::BatchItem *)(ws + lay.op);
+  B->d_vec = (semk::BatchItem *)(ws + lay.vec);
+  B->d_counts = (int *)(ws + lay.counts);
+  B->d_status = (semk::BatchStatus *)(ws + lay.status);
+  B->slots.assign(max_slots, semk::BatchSlot());
+  for (auto &S : B->slots) std::memset(&S, 0, sizeof(S));
+  B->ctx.assign(max_slots, nullptr);
+  B->status.assign(max_slots, semk::BatchStatus());
+  for (int n = 0; n <= semk::kMaxOrder; ++n) B->epb[n] = (n >= 1 && n <= 11) ? semk::batch_default_epb(n) : 1;
+  B->graph = nullptr;
+  B->graph_stream = nullptr;
+  B->graph_iters = 0;
+  hipError_t e = hipMemcpyAsync(B->d_slots, B->slots.data(), max_slots * sizeof(semk::BatchSlot),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    std::vector<semk::BatchStatus> zero(max_slots);
+    std::memset(zero.data(), 0, zero.size() * sizeof(semk::BatchStatus));
+    e = hipMemcpyAsync(B->d_status, zero.data(), zero.size() * sizeof(semk::BatchStatus),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) {
+    delete B;
+    return hip_fail(e, "sem_batch_create: initialise slot table");
+  }
+  int rc = batch_upload_items(B, s);
+  if (rc != SEM_OK) {
+    delete B;
+    return rc;
+  }
+  *out = B;
+  return SEM_OK;
+}
+
+int sem_batch_set_tile(sem_batch *B, int order, int elements_per_item) {
+  if (!B) return fail(SEM_ERR_ARG, "sem_batch_set_tile: null handle");
+  if (order < semk::kMinOrder || order > 11 || !semk::batch_epb_supported(order, elements_per_item))
+    return fail(SEM_ERR_UNSUPPORTED, "sem_batch_set_tile: tile not compiled for this order");
+  B->epb[order] = elements_per_item;
+  return SEM_OK;
+}
+
+int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts,
+                  int *slot_out, void *stream) {
+  if (!B || !ctx || !b || !x || !opts || !slot_out) return fail(SEM_ERR_ARG, "sem_batch_add: null argument");
+  if (ctx->in_batch) return fail(SEM_ERR_ARG, "sem_batch_add: the context is already in a batch");
+  if (b == x) return fail(SEM_ERR_ARG, "sem_batch_add: b and x must differ");
+  if (opts->fixed_iter > 0) return fail(SEM_ERR_ARG, "sem_batch_add: batches run in tolerance mode");
+  if (!(opts->rtol > 0.0)) return fail(SEM_ERR_ARG, "sem_batch_add: rtol must be > 0");
+  if (opts->mixed && ctx->desc.lowprec == SEM_F64)
+    return fail(SEM_ERR_ARG, "sem_batch_add: mixed precision needs a low-precision copy");
+  if (ctx->box.N > 11) return fail(SEM_ERR_UNSUPPORTED, "sem_batch_add: batches take orders 1..11");
+  int q = -1;
+  for (int i = 0; i < B->max_slots; ++i)
+    if (!B->ctx[i]) {
+      q = i;
+      break;
+    }
+  if (q < 0) return fail(SEM_ERR_NOMEM, "sem_batch_add: no free slot");
+  hipStream_t s = (hipStream_t)stream;
+  const Box &bx = ctx->box;
+  // start the solve exactly as sem_cg does
+  CgState &h = ctx->host_state;
+  std::memset(&h, 0, sizeof(h));
+  h.max_iter = opts->mixed ? (opts->max_iter > 0 ? opts->max_iter : 50)
+                           : (opts->max_iter > 0 ? opts->max_iter : 20000);
+  h.rtol2 = opts->rtol * opts->rtol;
+  SEM_HIP(hipMemcpyAsync(ctx->st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
+  SEM_HIP(semk::launch_cg_init(bx, b, x, ctx->r, ctx->p, ctx->minv, ctx->st, ctx->part_rz,
+                               ctx->part_rr, s));
+  SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+
+  semk::BatchSlot S;
+  std::memset(&S, 0, sizeof(S));
+  S.box = bx;
+  S.N = bx.N;
+  S.epb = B->epb[bx.N];
+  S.mixed = opts->mixed ? ctx->desc.lowprec : 0;
+  S.active = 1;
+  S.inner_total = 0;
+  S.inner_max = opts->inner_max > 0 ? opts->inner_max : 1000;
+  const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol
+                                            : (ctx->desc.lowprec == SEM_BF16 ? 1e-2 : 1e-3);
+  S.eta2 = eta * eta;
+  S.E = bx.E();
+  S.L = bx.L();
+  S.ntiles = semk::vec_grid_blocks(S.L);
+  S.D = ctx->D;
+  S.G = ctx->G;
+  S.b = b;
+  S.minv = ctx->minv;
+  S.r = ctx->r;
+  S.p = ctx->p;
+  S.w = ctx->w;
+  S.x = x;
+  S.Dlo = ctx->Dlo;
+  S.Glo = ctx->Glo;
+  S.minv32 = ctx->minv32;
+  S.e = ctx->e;
+  S.rin = ctx->rin;
+  S.pin = ctx->pin;
+  S.win = ctx->win;
+  S.st = ctx->st;
+  S.st_in = ctx->st_in;
+  S.part_el = ctx->part_ax;
+  S.part_rr = ctx->part_rr;
+  S.part_rz = ctx->part_rz;
+  if (h.done != semk::kRunning) S.phase = semk::kPhaseFinished;
+  else S.phase = S.mixed ? semk::kPhaseRestart : semk::kPhaseFp64;
+  semk::BatchStatus st0;
+  std::memset(&st0, 0, sizeof(st0));
+  st0.phase = S.phase;
+  st0.done = h.done;
+  st0.rnorm2 = h.rnorm2;
+  st0.bnorm2 = h.bnorm2;
+  SEM_HIP(hipMemcpyAsync(B->d_slots + q, &S, sizeof(S), hipMemcpyHostToDevice, s));
+  SEM_HIP(hipMemcpyAsync(B->d_status + q, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+  B->slots[q] = S;
+  B->ctx[q] = ctx;
+  ctx->in_batch = 1;
+  int rc = batch_upload_items(B, s);
+  if (rc != SEM_OK) {
+    B->ctx[q] = nullptr;
+    ctx->in_batch = 0;
+    S.active = 0;
+    (void)hipMemcpyAsync(B->d_slots + q, &S, sizeof(S), hipMemcpyHostToDevice, s);
+    (void)batch_upload_items(B, s);
+    return rc;
+  }
+  *slot_out = q;
+  return SEM_OK;
+}
+
+int sem_batch_step(sem_batch *B, int iters, void *stream) {
+  if (!B) return fail(SEM_ERR_ARG, "sem_batch_step: null handle");
+  if (iters < 1) return fail(SEM_ERR_ARG, "sem_batch_step: iters must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  if (s != nullptr && !(B->graph && B->graph_stream == s && B->graph_iters == iters)) {
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);
+    B->graph = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess) {
+      hipError_t e = hipSuccess;
+      for (int it = 0; it < iters && e == hipSuccess; ++it)
+        e = semk::launch_batch_iteration(B->d_slots, B->max_slots, B->d_op, B->d_vec, B->d_counts,
+                                         B->d_status, s);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(s, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e != hipSuccess ? e : e2, "sem_batch_step: capture");
+      }
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(e, "sem_batch_step: instantiate");
+      B->graph = ex;
+      B->graph_stream = s;
+      B->graph_iters = iters;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (B->graph && B->graph_stream == s && B->graph_iters == iters) {
+    SEM_HIP(hipGraphLaunch(B->graph, s));
+  } else {
+    for (int it = 0; it < iters; ++it)
+      SEM_HIP(semk::launch_batch_iteration(B->d_slots, B->max_slots, B->d_op, B->d_vec, B->d_counts,
+                                           B->d_status, s));
+  }
+  return SEM_OK;
+}
+
+int sem_batch_poll(sem_batch *B, int *finished, int cap, int *n_finished, sem_cg_info *infos,
+                   int *n_active, void *stream) {
+  if (!B || !n_finished) return fail(SEM_ERR_ARG, "sem_batch_poll: null argument");
+  if (cap > 0 && (!finished || !infos)) return fail(SEM_ERR_ARG, "sem_batch_poll: null output arrays");
+  hipStream_t s = (hipStream_t)stream;
+  SEM_HIP(hipMemcpyAsync(B->status.data(), B->d_status, B->max_slots * sizeof(semk::BatchStatus),
+                         hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  int nf = 0, na = 0;
+  for (int q = 0; q < B->max_slots; ++q) {
+    if (!B->ctx[q]) continue;
+    ++na;
+    const semk::BatchStatus &st = B->status[q];
+    if (st.phase != semk::kPhaseFinished) continue;
+    if (nf < cap) {
+      finished[nf] = q;
+      sem_cg_info &info = infos[nf];
+      info.iters = st.iters;
+      info.outer_iters = st.outer_iters;
+      info.rel_res = st.bnorm2 > 0.0 ? std::sqrt(st.rnorm2 / st.bnorm2) : 0.0;
+      info.status = st.done == semk::kBreakdown ? SEM_ERR_BREAKDOWN
+                    : st.done == semk::kMaxIter ? SEM_ERR_NOTCONV : SEM_OK;
+      info.reserved = 0;
+    }
+    ++nf;
+  }
+  *n_finished = nf < cap ? nf : (cap > 0 ? cap : 0);
+  if (n_active) *n_active = na;
+  return SEM_OK;
+}
+
+int sem_batch_remove(sem_batch *B, int slot, void *stream) {
+  if (!B) return fail(SEM_ERR_ARG, "sem_batch_remove: null handle");
+  if (slot < 0 || slot >= B->max_slots || !B->ctx[slot]) return fail(SEM_ERR_ARG, "sem_batch_remove: no such slot");
+  hipStream_t s = (hipStream_t)stream;
+  semk::BatchSlot S;
+  std::memset(&S, 0, sizeof(S));
+  SEM_HIP(hipMemcpyAsync(B->d_slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
+  B->slots[slot] = S;
+  B->ctx[slot]->in_batch = 0;
+  B->ctx[slot] = nullptr;
+  return batch_upload_items(B, s);
+}
+
+int sem_batch_destroy(sem_batch *B) {
+  if (!B) return fail(SEM_ERR_ARG, "sem_batch_destroy: null handle");
+  for (auto *c : B->ctx)
+    if (c) c->in_batch = 0;
+  if (B->graph) (void)hipGraphExecDestroy(B->graph);
+  delete B;
   return SEM_OK;
 }
 

@@ -9,18 +9,11 @@
 // of the element (element-major layout, i fastest).
 #include <hip/hip_runtime.h>
 
+#include "sem_ax_tile.h"
 #include "sem_device.h"
 #include "sem_internal.h"
 
 namespace semk {
-
-template <int N1>
-struct AxTile {
-  static constexpr int P = N1 + 1;      // padded row (LDS bank spread)
-  static constexpr int PLANE = N1 * P;  // one k-plane of the padded tile
-  static constexpr int TILE = N1 * PLANE;
-  static constexpr int NP = N1 * N1 * N1;
-};
 
 namespace {
 
@@ -32,147 +25,6 @@ struct AxCfg {
 };
 
 }  // namespace
-
-// The operator on one tile of EPB consecutive elements starting at e0,
-// computed by the first N1*N1*EPB threads of the work-group (any others
-// only join the barriers).  Shared by the per-order kernels below and the
-// batched persistent kernel, so both produce the same bits.
-//   CG: prologue x += alpha p_old, p = Minv r + beta p_old (u is p), and the
-//   per-element sums of p.(A_L p) go to part_el[e] (summed in a fixed tree).
-// sD: N1*N1, s1/s2: EPB * AxTile<N1>::TILE values of TC, sred: blockDim
-// doubles, all in LDS.
-template <int N1, int EPB, class P, bool CG>
-__device__ __forceinline__ void ax_tile(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
-                                        const typename P::TG *__restrict__ G, typename P::TV *u,
-                                        typename P::TV *__restrict__ w,
-                                        const typename P::TV *__restrict__ r,
-                                        const typename P::TV *__restrict__ minv,
-                                        typename P::TV *__restrict__ x, double alpha_d, double beta_d,
-                                        double *__restrict__ part_el, typename P::TC *sD,
-                                        typename P::TC *s1, typename P::TC *s2, double *sred) {
-  using T = AxTile<N1>;
-  using TV = typename P::TV;
-  using TC = typename P::TC;
-  constexpr int NP = T::NP;
-  constexpr int PL = N1 * N1;
-  const int tid = threadIdx.x;
-  const int el = tid / PL;
-  const int ij = tid - el * PL;
-  const int i = ij % N1;
-  const int j = ij / N1;
-  const int64_t e = e0 + el;
-  const bool active = el < EPB && e < E;
-
-  for (int t = tid; t < N1 * N1; t += blockDim.x) sD[t] = Dg[t];
-
-  const int64_t base = e * NP + ij;
-  TC uk[N1];  // the operand (p in CG), in the contraction type
-  TC g[6][N1];
-  if (active) {
-    if (CG) {
-      const TV beta = (TV)beta_d, alpha = (TV)alpha_d;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        const int64_t idx = base + k * PL;
-        const TV pold = u[idx];
-        x[idx] += alpha * pold;
-        const TV v = minv[idx] * r[idx] + beta * pold;
-        uk[k] = (TC)v;
-        u[idx] = v;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < N1; ++k) uk[k] = (TC)u[base + k * PL];
-    }
-    const typename P::TG *Ge = G + e * 6 * NP + ij;
-#pragma unroll
-    for (int q = 0; q < 6; ++q)
-#pragma unroll
-      for (int k = 0; k < N1; ++k) g[q][k] = load_g<P>(Ge + q * NP + k * PL);
-  } else {
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      uk[k] = (TC)0;
-#pragma unroll
-      for (int q = 0; q < 6; ++q) g[q][k] = (TC)0;
-    }
-  }
-
-  TC uc[N1];  // contraction input (rounded to bfloat16 in that mode)
-#pragma unroll
-  for (int k = 0; k < N1; ++k) uc[k] = contraction_input<P>(uk[k]);
-
-  const int slot = el < EPB ? el : 0;  // idle threads alias slot 0 but never write
-  TC *S1 = s1 + slot * T::TILE;
-  TC *S2 = s2 + slot * T::TILE;
-  if (el < EPB) {
-#pragma unroll
-    for (int k = 0; k < N1; ++k) S1[k * T::PLANE + j * T::P + i] = uc[k];
-  }
-  __syncthreads();
-
-  TC Da[N1], Db[N1];
-#pragma unroll
-  for (int l = 0; l < N1; ++l) {
-    Da[l] = sD[i * N1 + l];
-    Db[l] = sD[j * N1 + l];
-  }
-  TC wr[N1], ws[N1], wt[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    TC ur = 0, us = 0, ut = 0;
-#pragma unroll
-    for (int l = 0; l < N1; ++l) {
-      ur += Da[l] * S1[k * T::PLANE + j * T::P + l];
-      us += Db[l] * S1[k * T::PLANE + l * T::P + i];
-      ut += sD[k * N1 + l] * uc[l];
-    }
-    wr[k] = contraction_input<P>(g[0][k] * ur + g[1][k] * us + g[2][k] * ut);
-    ws[k] = contraction_input<P>(g[1][k] * ur + g[3][k] * us + g[4][k] * ut);
-    wt[k] = contraction_input<P>(g[2][k] * ur + g[4][k] * us + g[5][k] * ut);
-  }
-  __syncthreads();
-  if (el < EPB) {
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      S1[k * T::PLANE + j * T::P + i] = wr[k];
-      S2[k * T::PLANE + j * T::P + i] = ws[k];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int l = 0; l < N1; ++l) {
-    Da[l] = sD[l * N1 + i];
-    Db[l] = sD[l * N1 + j];
-  }
-  double acc = 0.0;
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    TC v = 0;
-#pragma unroll
-    for (int l = 0; l < N1; ++l) {
-      v += Da[l] * S1[k * T::PLANE + j * T::P + l];
-      v += Db[l] * S2[k * T::PLANE + l * T::P + i];
-      v += sD[l * N1 + k] * wt[l];
-    }
-    if (active) w[base + k * PL] = (TV)v;
-    acc += (double)uk[k] * (double)v;
-  }
-  if (CG) {
-    // per-element sum of p.(A_L p): fixed tree over the element's threads
-    sred[tid] = acc;
-    __syncthreads();
-    constexpr int P2 = next_pow2(PL);
-    const int lt = ij;
-#pragma unroll
-    for (int s = P2 / 2; s > 0; s >>= 1) {
-      if (el < EPB && lt < s && lt + s < PL) sred[tid] += sred[tid + s];
-      __syncthreads();
-    }
-    if (active && lt == 0) part_el[e] = sred[tid];
-  }
-  __syncthreads();  // LDS is free for the next tile
-}
 
 namespace {
 
@@ -187,6 +39,7 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   __shared__ TC sD[N1 * N1];
   __shared__ TC s1[C::EPB * AxTile<N1>::TILE];
   __shared__ TC s2[C::EPB * AxTile<N1>::TILE];
+  __shared__ TC s3[AxTile<N1>::kTiles == 3 ? C::EPB * AxTile<N1>::TILE : 1];
   __shared__ double sred[CG ? C::THREADS : 1];
   double alpha = 0.0, beta = 0.0;
   if (CG) {
@@ -195,7 +48,7 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
     beta = st->beta;
   }
   ax_tile<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha, beta,
-                             part, sD, s1, s2, sred);
+                             part, sD, s1, s2, s3, sred);
 }
 
 // Rounded copy of G for a low-precision operator.

@@ -86,6 +86,68 @@ inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) 
 // Jacobi inverse 1/sum with boundary nodes zeroed (inverse).
 enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse = 2 };
 
+// ---------------------------------------------------------------- batches
+// Phase of a solve inside a batch (advanced on the device).
+enum SlotPhase : int {
+  kPhaseFp64 = 0,       // FP64 Jacobi-PCG iterations
+  kPhaseFp64Done = 1,   // FP64 solve stopped: the last x += alpha p is pending
+  kPhaseInner = 2,      // inner low-precision PCG iterations
+  kPhaseInnerDone = 3,  // inner solve stopped: x += ||r|| (e + alpha p) pending
+  kPhaseOuterOp = 4,    // FP64 true residual of the corrected x
+  kPhaseRestart = 5,    // inner restart r_in = r / ||r|| pending
+  kPhaseFinished = 6,   // nothing left to do
+};
+
+// One solve of a batch: the operator data of its sem_ctx plus its vectors.
+struct BatchSlot {
+  Box box;
+  int N;
+  int epb;    // elements per operator item
+  int mixed;  // 0: FP64, else the low-precision copy's sem_prec
+  int active;
+  int phase;  // SlotPhase, written by the device
+  int inner_total;
+  int inner_max;
+  int pad;
+  double eta2;
+  int64_t E, L, ntiles;  // ntiles: streaming partial count (vec_grid_blocks(L))
+  const double *D, *G, *b;
+  double *minv, *r, *p, *w, *x;
+  const float *Dlo;
+  const void *Glo;
+  float *minv32, *e, *rin, *pin, *win;
+  CgState *st, *st_in;
+  double *part_el, *part_rr, *part_rz;
+};
+
+struct BatchItem {
+  int slot;
+  int first;  // first element (operator items) or tile index (streaming items)
+};
+
+// Compact per-slot status the host polls (written by the device).
+struct BatchStatus {
+  int phase;
+  int done;
+  int iters;        // FP64 iterations, or total inner iterations (mixed)
+  int outer_iters;  // mixed: outer steps
+  double rnorm2, bnorm2;
+};
+
+// Persistent launch sizes of the batched kernels.
+constexpr int kBatchOpBlocks = 2048;
+constexpr int kBatchVecBlocks = 2048;
+
+// Candidate operator tiles (elements per 256-thread work-group) per order;
+// batches take orders 1..11.
+int batch_default_epb(int N);
+bool batch_epb_supported(int N, int epb);
+
+// One batched iteration (seven launches) over every active slot.
+hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchItem *op_items,
+                                  const BatchItem *vec_items, const int *counts,
+                                  BatchStatus *status, hipStream_t s);
+
 // ---------------------------------------------------------------- launchers
 // All return the hipError_t of the launch (hipGetLastError after it).
 
@@ -125,34 +187,31 @@ hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r
 // partials of ||r||_c^2 and <r, Minv r>_c.  Skipped when done.
 hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s);
-// After the last iteration: x += alpha p if that iteration's update ran.
-hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
-                            hipStream_t s);
-// FP32 versions for the inner solver of the inner-outer CG.
-hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
-                                CgState *st, double *part_rr, double *part_rz, hipStream_t s);
-hipError_t launch_cg_finish_f32(const Box &b, float *x, const float *p, const CgState *st,
-                                hipStream_t s);
-
-// Inner-outer CG steps.  inner_start: reset the inner state (tolerance
-// rtol2 = eta^2, iteration cap), r_in = r / ||r||_c in FP32, e = p = 0, and
-// rho, ||r_in||_c of the inner state.  outer_update: x += ||r||_c e.
-// outer_step (after w64 = A_L x): r = mask o (b - QQ^T w64), ||r||_c^2, the
-// outer count and the done flag of the outer state.
-hipError_t launch_inner_start(const Box &b, const double *r64, CgState *outer, CgState *inner,
-                              double rtol2, int max_iter, float *rin, float *e, float *p,
-                              const float *minv32, double *part_a, double *part_b, hipStream_t s);
-hipError_t launch_outer_update(const Box &b, double *x, const float *e, const CgState *outer,
-                               hipStream_t s);
-hipError_t launch_outer_step(const Box &b, double *x, const float *e, const double *bvec,
-                             const double *w64, double *r64, CgState *outer, double *part,
-                             hipStream_t s);
 // One-group launches that finish the reductions and advance the scalars:
 // alpha = rho / <p, A p> (breakdown check), and after the update
 // iteration count, ||r||_c, rho, beta and the done flag.
 hipError_t launch_cg_alpha(CgState *st, const double *part_pap, int64_t n, hipStream_t s);
 hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part_rz, int64_t n,
                           hipStream_t s);
+// After the last iteration: x += alpha p if that iteration's update ran.
+hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
+                            hipStream_t s);
+// FP32 update for the inner solver of the inner-outer CG.
+hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
+                                CgState *st, double *part_rr, double *part_rz, hipStream_t s);
+
+// Inner-outer CG steps.  inner_start: r_in = r / ||r||_c in FP32, e = p = 0,
+// then the inner state: tolerance rtol2 = eta^2 (relative), iteration cap,
+// rho.  outer_correct: e += alpha_in p_in (if the inner solve's last update
+// ran), x += ||r||_c e.  outer_step (after w64 = A_L x): r = mask o (b -
+// QQ^T w64), ||r||_c^2, the outer count and the done flag.
+hipError_t launch_inner_start(const Box &b, const double *r64, CgState *outer, CgState *inner,
+                              double rtol2, int max_iter, float *rin, float *e, float *p,
+                              const float *minv32, double *part_a, double *part_b, hipStream_t s);
+hipError_t launch_outer_correct(const Box &b, double *x, float *e, const float *p,
+                                const CgState *inner, const CgState *outer, hipStream_t s);
+hipError_t launch_outer_step(const Box &b, const double *bvec, const double *w64, double *r64,
+                             CgState *outer, double *part, hipStream_t s);
 
 // Generic vectors.
 hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);

@@ -14,6 +14,7 @@
 // one-group launch.  Results depend only on the data and the sizes.
 #include <hip/hip_runtime.h>
 
+#include "sem_cg_dev.h"
 #include "sem_device.h"
 #include "sem_internal.h"
 
@@ -49,55 +50,23 @@ template <int N1>
 __global__ void __launch_bounds__(kVecThreads)
     cg_init_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ bvec,
                    double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                   const double *__restrict__ minv, CgState *__restrict__ st,
-                   double *__restrict__ part_rz, double *__restrict__ part_bb) {
+                   const double *__restrict__ minv, double *__restrict__ part_rz,
+                   double *__restrict__ part_bb) {
   __shared__ double sred[kVecThreads / 64];
   const int64_t tile = xcd_tile(ntiles);
-  double rz = 0.0, bb = 0.0;
-  if (tile < ntiles) {
-    const int64_t base = tile * kVecTile + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-      const int64_t idx = base + (int64_t)u * kVecThreads;
-      if (idx < L) {
-        const Node<N1> n = node_at<N1>(b, idx);
-        const double c = 1.0 / (double)n.mult;
-        const double rv = n.boundary ? 0.0 : bvec[idx];
-        x[idx] = 0.0;
-        r[idx] = rv;
-        p[idx] = 0.0;
-        rz += c * rv * (minv[idx] * rv);
-        bb += c * rv * rv;
-      }
-    }
-  }
-  const double a = block_sum<kVecThreads>(rz, sred);
-  const double c = block_sum<kVecThreads>(bb, sred);
+  TileSums t{0.0, 0.0};
+  if (tile < ntiles) t = cg_init_tile<N1>(b, L, tile, bvec, x, r, p, minv, sred);
   if (threadIdx.x == 0) {
-    part_rz[tile] = a;
-    part_bb[tile] = c;
+    part_rz[tile] = t.a;
+    part_bb[tile] = t.b;
   }
 }
-
-constexpr int kFinThreads = 1024;
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_init_finish_kernel(CgState *st, const double *__restrict__ part_rz,
                           const double *__restrict__ part_bb, int64_t n) {
   __shared__ double sred[kFinThreads / 64];
-  const double rho = sum_partials<kFinThreads>(part_rz, n, sred);
-  const double bn = sum_partials<kFinThreads>(part_bb, n, sred);
-  if (threadIdx.x == 0) {
-    st->rho = rho;
-    st->bnorm2 = bn;
-    st->rnorm2 = bn;
-    st->beta = 0.0;
-    st->alpha = 0.0;
-    st->iter = 0;
-    st->tol2 = st->rtol2 * bn;
-    st->done = (bn == 0.0) ? kConverged : kRunning;
-    if (!isfinite(bn) || !isfinite(rho)) st->done = kBreakdown;
-  }
+  cg_init_step(st, part_rz, part_bb, n, sred);
 }
 
 template <int N1, typename TV>
@@ -110,110 +79,40 @@ __global__ void __launch_bounds__(kVecThreads)
   if (st->done) return;
   const double alpha = st->alpha;
   const int64_t tile = xcd_tile(ntiles);
-  double rr = 0.0, rz = 0.0;
-  if (tile < ntiles) {
-    const int64_t base = tile * kVecTile + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-      const int64_t idx = base + (int64_t)u * kVecThreads;
-      if (idx < L) {
-        const Node<N1> n = node_at<N1>(b, idx);
-        if (!n.boundary) {
-          const double wa = gather_copies<N1>(w, b, n, idx);
-          const TV rt = (TV)((double)r[idx] - alpha * wa);
-          r[idx] = rt;
-          const double rv = (double)rt;
-          const double c = 1.0 / (double)n.mult;
-          rr += c * rv * rv;
-          rz += c * rv * ((double)minv[idx] * rv);
-        }
-      }
-    }
-  }
-  const double a = block_sum<kVecThreads>(rr, sred);
-  const double c = block_sum<kVecThreads>(rz, sred);
+  TileSums t{0.0, 0.0};
+  if (tile < ntiles) t = cg_update_tile<N1, TV>(b, L, tile, r, w, minv, alpha, sred);
   if (threadIdx.x == 0) {
-    part_rr[tile] = a;
-    part_rz[tile] = c;
+    part_rr[tile] = t.a;
+    part_rz[tile] = t.b;
   }
 }
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_alpha_kernel(CgState *st, const double *__restrict__ part, int64_t n) {
   __shared__ double sred[kFinThreads / 64];
-  // the state loads are independent of the partial sums: issue them first
-  const int done = st->done;
-  const double rho = st->rho;
-  const double pap = sum_partials<kFinThreads>(part, n, sred);
-  if (threadIdx.x == 0 && done == kRunning) {
-    st->pap = pap;
-    if (!(pap > 0.0) || !isfinite(pap)) {
-      st->done = kBreakdown;
-      st->done_stage = 1;
-    } else {
-      st->alpha = rho / pap;
-    }
-  }
+  cg_alpha_step(st, part, n, sred);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_beta_kernel(CgState *st, const double *__restrict__ part_rr,
                    const double *__restrict__ part_rz, int64_t n) {
   __shared__ double sred[kFinThreads / 64];
-  const int done = st->done;
-  const int it = st->iter + 1;
-  const int max_iter = st->max_iter;
-  const double rho = st->rho, tol2 = st->tol2;
-  const double rrt = sum_partials<kFinThreads>(part_rr, n, sred);
-  const double rzt = sum_partials<kFinThreads>(part_rz, n, sred);
-  if (threadIdx.x == 0 && done == kRunning) {
-    st->iter = it;
-    st->rnorm2 = rrt;
-    const double beta = rzt / rho;
-    st->beta = beta;
-    st->rho = rzt;
-    if (!isfinite(rrt) || !isfinite(beta)) {
-      st->done = kBreakdown;
-    } else if (tol2 >= 0.0 && rrt <= tol2) {
-      st->done = kConverged;
-    } else if (it >= max_iter) {
-      st->done = kMaxIter;
-    }
-    st->done_stage = 2;
-  }
+  cg_beta_step(st, part_rr, part_rz, n, sred);
 }
 
-// Outer step of the inner-outer solve: ||r||_c^2 of the true residual, the
-// outer count and the done flag.
 __global__ void __launch_bounds__(kFinThreads)
     outer_finish_kernel(CgState *st, const double *__restrict__ part, int64_t n) {
   __shared__ double sred[kFinThreads / 64];
-  const int done = st->done;
-  const int it = st->iter + 1;
-  const int max_iter = st->max_iter;
-  const double tol2 = st->tol2;
-  const double rr = sum_partials<kFinThreads>(part, n, sred);
-  if (threadIdx.x == 0 && done == kRunning) {
-    st->iter = it;
-    st->rnorm2 = rr;
-    if (!isfinite(rr)) {
-      st->done = kBreakdown;
-    } else if (rr <= tol2) {
-      st->done = kConverged;
-    } else if (it >= max_iter) {
-      st->done = kMaxIter;
-    }
-  }
+  outer_finish_step(st, part, n, sred);
 }
 
 // The last x += alpha p of a solve (the operator kernel folds it into the
 // next iteration's prologue, and there is no next iteration).
-template <typename TV>
 __global__ void __launch_bounds__(kVecThreads)
-    cg_finish_kernel(int64_t L, TV *__restrict__ x, const TV *__restrict__ p,
+    cg_finish_kernel(int64_t L, double *__restrict__ x, const double *__restrict__ p,
                      const CgState *__restrict__ st) {
   if (st->done == kRunning || st->done_stage != 2) return;
-  const TV alpha = (TV)st->alpha;
+  const double alpha = st->alpha;
   const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
 #pragma unroll
   for (int u = 0; u < kVecItems; ++u) {
@@ -223,21 +122,6 @@ __global__ void __launch_bounds__(kVecThreads)
 }
 
 // ------------------------------------------------------------ inner-outer CG
-// Reset the inner solver's state for a new outer step.
-__global__ void inner_reset_kernel(CgState *st, double rtol2, int max_iter) {
-  if (threadIdx.x == 0) {
-    st->done = kRunning;
-    st->iter = 0;
-    st->done_stage = 0;
-    st->max_iter = max_iter;
-    st->rtol2 = rtol2;
-    st->alpha = 0.0;
-    st->beta = 0.0;
-  }
-}
-
-// Inner start: r_in = r / ||r||_c in FP32, e = 0, p = 0, partials of
-// <r_in, Minv r_in>_c and ||r_in||_c^2 (FP64 accumulation).
 template <int N1>
 __global__ void __launch_bounds__(kVecThreads)
     inner_start_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ r64,
@@ -248,44 +132,29 @@ __global__ void __launch_bounds__(kVecThreads)
   __shared__ double sred[kVecThreads / 64];
   const double inv_s = 1.0 / sqrt(outer->rnorm2);
   const int64_t tile = xcd_tile(ntiles);
-  double rz = 0.0, rr = 0.0;
-  if (tile < ntiles) {
-    const int64_t base = tile * kVecTile + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-      const int64_t idx = base + (int64_t)u * kVecThreads;
-      if (idx < L) {
-        const Node<N1> n = node_at<N1>(b, idx);
-        const float rv = (float)(r64[idx] * inv_s);
-        rin[idx] = rv;
-        e[idx] = 0.0f;
-        p[idx] = 0.0f;
-        const double c = 1.0 / (double)n.mult;
-        rz += c * (double)rv * ((double)minv32[idx] * (double)rv);
-        rr += c * (double)rv * (double)rv;
-      }
-    }
-  }
-  const double a = block_sum<kVecThreads>(rz, sred);
-  const double c = block_sum<kVecThreads>(rr, sred);
+  TileSums t{0.0, 0.0};
+  if (tile < ntiles) t = inner_start_tile<N1>(b, L, tile, r64, inv_s, rin, e, p, minv32, sred);
   if (threadIdx.x == 0) {
-    part_rz[tile] = a;
-    part_rr[tile] = c;
+    part_rz[tile] = t.a;
+    part_rr[tile] = t.b;
   }
 }
 
-// x += ||r||_c e (the scaled inner correction), in FP64.
+__global__ void __launch_bounds__(kFinThreads)
+    inner_init_kernel(CgState *st, const double *__restrict__ part_rz,
+                      const double *__restrict__ part_rr, int64_t n, double rtol2, int max_iter) {
+  __shared__ double sred[kFinThreads / 64];
+  inner_init_step(st, part_rz, part_rr, n, rtol2, max_iter, sred);
+}
+
+// e += alpha_in p_in (if the inner solve's last update ran), x += ||r||_c e.
 __global__ void __launch_bounds__(kVecThreads)
-    outer_update_kernel(int64_t L, double *__restrict__ x, const float *__restrict__ e,
-                        const CgState *__restrict__ outer) {
+    outer_correct_kernel(int64_t L, double *__restrict__ x, float *__restrict__ e,
+                         const float *__restrict__ p, const CgState *__restrict__ inner,
+                         const CgState *__restrict__ outer) {
   if (outer->done != kRunning) return;
-  const double s = sqrt(outer->rnorm2);
-  const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kVecItems; ++u) {
-    const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < L) x[idx] += s * (double)e[idx];
-  }
+  const bool add_p = inner->done != kRunning && inner->done_stage == 2;
+  outer_correct_tile(L, blockIdx.x, x, e, p, (float)inner->alpha, add_p, sqrt(outer->rnorm2));
 }
 
 // True residual r = mask o (b - QQ^T w_L) with w_L = A_L x (FP64) and the
@@ -299,22 +168,8 @@ __global__ void __launch_bounds__(kVecThreads)
   const int done = outer->done;
   const int64_t tile = xcd_tile(ntiles);
   double rr = 0.0;
-  if (tile < ntiles && done == kRunning) {
-    const int64_t base = tile * kVecTile + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-      const int64_t idx = base + (int64_t)u * kVecThreads;
-      if (idx < L) {
-        const Node<N1> n = node_at<N1>(b, idx);
-        double rv = 0.0;
-        if (!n.boundary) rv = bvec[idx] - gather_copies<N1>(wl, b, n, idx);
-        r[idx] = rv;
-        rr += rv * rv / (double)n.mult;
-      }
-    }
-  }
-  const double a = block_sum<kVecThreads>(rr, sred);
-  if (threadIdx.x == 0) part[tile] = a;
+  if (tile < ntiles && done == kRunning) rr = residual_tile<N1>(b, L, tile, bvec, wl, r, sred);
+  if (threadIdx.x == 0) part[tile] = rr;
 }
 
 // ------------------------------------------------------------ setup helpers
@@ -460,7 +315,7 @@ hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r
   const int64_t L = b.L();
   const int64_t nt = vec_num_blocks(L);
   DISPATCH_N(b, cg_init_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, bvec, x, r, p,
-             minv, st, part_a, part_b);
+             minv, part_a, part_b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, st, part_a, part_b,
@@ -500,14 +355,7 @@ hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const fl
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
                             hipStream_t s) {
   const int64_t L = b.L();
-  hipLaunchKernelGGL(cg_finish_kernel<double>, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_finish_f32(const Box &b, float *x, const float *p, const CgState *st,
-                                hipStream_t s) {
-  const int64_t L = b.L();
-  hipLaunchKernelGGL(cg_finish_kernel<float>, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
+  hipLaunchKernelGGL(cg_finish_kernel, vec_grid(L), dim3(kVecThreads), 0, s, L, x, p, st);
   return hipGetLastError();
 }
 
@@ -516,21 +364,25 @@ hipError_t launch_inner_start(const Box &b, const double *r64, CgState *outer, C
                               const float *minv32, double *part_a, double *part_b, hipStream_t s) {
   const int64_t L = b.L();
   const int64_t nt = vec_num_blocks(L);
-  hipLaunchKernelGGL(inner_reset_kernel, dim3(1), dim3(64), 0, s, inner, rtol2, max_iter);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
   DISPATCH_N(b, inner_start_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, r64, outer,
              rin, e, p, minv32, part_a, part_b);
-  err = hipGetLastError();
+  hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, inner, part_a, part_b,
-                     vec_grid_blocks(L));
+  hipLaunchKernelGGL(inner_init_kernel, dim3(1), dim3(kFinThreads), 0, s, inner, part_a, part_b,
+                     vec_grid_blocks(L), rtol2, max_iter);
   return hipGetLastError();
 }
 
-hipError_t launch_outer_step(const Box &b, double *x, const float *e, const double *bvec,
-                             const double *w64, double *r64, CgState *outer, double *part,
-                             hipStream_t s) {
+hipError_t launch_outer_correct(const Box &b, double *x, float *e, const float *p,
+                                const CgState *inner, const CgState *outer, hipStream_t s) {
+  const int64_t L = b.L();
+  hipLaunchKernelGGL(outer_correct_kernel, vec_grid(L), dim3(kVecThreads), 0, s, L, x, e, p, inner,
+                     outer);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_step(const Box &b, const double *bvec, const double *w64, double *r64,
+                             CgState *outer, double *part, hipStream_t s) {
   const int64_t L = b.L();
   const int64_t nt = vec_num_blocks(L);
   DISPATCH_N(b, residual_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, bvec, w64, r64,
@@ -539,15 +391,6 @@ hipError_t launch_outer_step(const Box &b, double *x, const float *e, const doub
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(outer_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, outer, part,
                      vec_grid_blocks(L));
-  (void)x;
-  (void)e;
-  return hipGetLastError();
-}
-
-hipError_t launch_outer_update(const Box &b, double *x, const float *e, const CgState *outer,
-                               hipStream_t s) {
-  const int64_t L = b.L();
-  hipLaunchKernelGGL(outer_update_kernel, vec_grid(L), dim3(kVecThreads), 0, s, L, x, e, outer);
   return hipGetLastError();
 }
 

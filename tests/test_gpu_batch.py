@@ -1,0 +1,190 @@
+"""GPU tests of the batching form: many uneven solves in one batched step.
+
+- An FP64 solve in a batch gives the same bits as alone (same device
+  functions, same tiles, same reduction order), for every order 1..11,
+  whatever the operator tile size and whatever else is in the batch.
+- A mixed-precision solve likewise matches its single run.
+- Solves join and leave while others run (continuous batching); failures
+  (breakdown) stay confined to their slot.
+- Small batched solves agree with the FP64 oracle.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workload
+from oracle import operator as op, pcg as opcg
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2606_12650_amd as sem
+    from paper_2606_12650_amd import _lib as L
+    from paper_2606_12650_amd.batch import SemBatch, default_epb, items_for
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"[gpu-test] {os.environ.get('PYTEST_CURRENT_TEST', '')}", flush=True)
+
+
+def _instance(i, nx, ny, nz, N, amp=0.05, lowprec=None):
+    A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=lowprec, device=DEV)
+    b = torch.from_numpy(workload.continuous_rhs(500 + i, nx, ny, nz, N)).to(DEV)
+    return A, b
+
+
+MESHES = [((3, 2, 2), 1), ((2, 3, 2), 2), ((2, 2, 3), 3), ((3, 3, 2), 4), ((2, 2, 2), 5),
+          ((3, 2, 3), 6), ((2, 3, 3), 7), ((2, 2, 2), 8), ((2, 2, 3), 9), ((2, 2, 2), 10),
+          ((2, 3, 2), 11)]
+
+
+def test_fp64_batched_equals_alone_all_orders():
+    insts = [_instance(i, *m, N) for i, (m, N) in enumerate(MESHES)]
+    alone = []
+    for A, b in insts:
+        x, res = A.cg(b, rtol=1e-8)
+        alone.append((x.clone(), res))
+    nop = sum(items_for(A, default_epb(A.order))[0] for A, _ in insts)
+    nvec = sum(items_for(A, 1)[1] for A, _ in insts)
+    B = SemBatch(len(insts) + 2, nop + 16, nvec + 16, device=DEV)
+    slots = [B.add(A, b) for A, b in insts]
+    res = B.run_all(iters_per_step=7)
+    for k, (s, (xa, ra)) in enumerate(zip(slots, alone)):
+        rb = res[s]
+        assert rb.status == 0 and rb.iters == ra.iters, (k, rb, ra)
+        assert torch.equal(B.solution(s), xa), k
+        assert rb.rel_res == ra.rel_res
+    for s in slots:
+        B.remove(s)
+    # the contexts run alone again after removal
+    x, r = insts[0][0].cg(insts[0][1], rtol=1e-8)
+    assert torch.equal(x, alone[0][0])
+
+
+@pytest.mark.parametrize("order,tile", [(3, 16), (5, 7), (7, 4), (9, 2)])
+def test_tile_shape_does_not_change_bits(order, tile):
+    A, b = _instance(7, 3, 2, 2, order)
+    x0, r0 = A.cg(b, rtol=1e-8)
+    x0 = x0.clone()
+    B = SemBatch(2, 64, 64, device=DEV)
+    B.set_tile(order, tile)
+    s = B.add(A, b)
+    res = B.run_all(iters_per_step=10)
+    assert res[s].iters == r0.iters and torch.equal(B.solution(s), x0)
+    B.remove(s)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_batched_matches_alone(prec):
+    cases = [((3, 3, 2), 5), ((2, 3, 3), 7), ((2, 2, 3), 3), ((2, 2, 2), 9)]
+    insts = [_instance(20 + i, *m, N, lowprec=prec) for i, (m, N) in enumerate(cases)]
+    alone = []
+    for A, b in insts:
+        x, r = A.cg(b, rtol=1e-8, mixed=True)
+        alone.append((x.clone(), r))
+    B = SemBatch(8, 512, 512, device=DEV)
+    slots = [B.add(A, b, mixed=True) for A, b in insts]
+    res = B.run_all(iters_per_step=9)
+    for s, (xa, ra), (A, b) in zip(slots, alone, insts):
+        rb = res[s]
+        assert rb.status == 0 and rb.rel_res <= 1e-8
+        assert rb.iters == ra.iters and rb.outer_iters == ra.outer_iters, (rb, ra)
+        assert torch.equal(B.solution(s), xa)
+
+
+def test_continuous_batching_join_leave_and_isolation():
+    """Solves join while others run; a solve that breaks down (NaN in its
+    right-hand side) leaves the others untouched."""
+    specs = [((3, 2, 2), 3, None), ((2, 2, 3), 5, "f32"), ((2, 3, 2), 7, None), ((2, 2, 2), 9, "bf16"),
+             ((3, 2, 2), 11, None), ((2, 2, 2), 4, None)]
+    insts = []
+    for i, (m, N, lp) in enumerate(specs):
+        A, b = _instance(40 + i, *m, N, lowprec=lp)
+        insts.append((A, b, lp))
+    alone = []
+    for A, b, lp in insts:
+        x, r = A.cg(b, rtol=1e-8, mixed=lp is not None)
+        alone.append(x.clone())
+    bad_A, bad_b = _instance(99, 2, 2, 2, 5)
+    bad_b[int(torch.nonzero(bad_b)[0])] = float("nan")
+    B = SemBatch(8, 2048, 2048, device=DEV)
+    slot_of = {}
+    for k in range(3):
+        A, b, lp = insts[k]
+        slot_of[B.add(A, b, mixed=lp is not None)] = k
+    bad_slot = B.add(bad_A, bad_b)
+    B.step(5)
+    pending = list(range(3, len(insts)))
+    done = {}
+    for _ in range(10000):
+        fin, active = B.poll()
+        for s, r in fin:
+            if s == bad_slot:
+                assert r.status == L.SEM_ERR_BREAKDOWN
+                B.remove(s)
+                bad_slot = None
+                continue
+            k = slot_of.pop(s)
+            assert r.status == 0, (k, r)
+            x = B.remove(s)[2]
+            done[k] = x
+            if pending:  # a finished slot is refilled at once
+                k2 = pending.pop(0)
+                A, b, lp = insts[k2]
+                slot_of[B.add(A, b, mixed=lp is not None)] = k2
+        if len(done) == len(insts):
+            break
+        B.step(3)
+    assert len(done) == len(insts) and bad_slot is None
+    for k in range(len(insts)):
+        assert torch.equal(done[k], alone[k]), k
+
+
+def test_batched_vs_oracle_small():
+    cases = [((2, 2, 2), 3), ((2, 3, 2), 5)]
+    B = SemBatch(4, 64, 64, device=DEV)
+    data = []
+    for i, ((nx, ny, nz), N) in enumerate(cases):
+        pr = op.Problem(nx, ny, nz, N, 0.05)
+        bn = workload.continuous_rhs(70 + i, nx, ny, nz, N)
+        xr, _ = opcg.pcg(pr.ax, pr.shape4(bn), pr.minv, pr.c, rtol=1e-12)
+        A = sem.SemOperator(nx, ny, nz, N, 0.05, device=DEV)
+        b = torch.from_numpy(bn).to(DEV)
+        data.append((pr, xr, B.add(A, b), A, b))
+    res = B.run_all(iters_per_step=5)
+    for pr, xr, s, A, b in data:
+        assert res[s].status == 0
+        x = B.solution(s).cpu().numpy()
+        c = pr.c.reshape(-1)
+        err = math.sqrt(np.sum(c * (x - xr.reshape(-1)) ** 2) / np.sum(c * xr.reshape(-1) ** 2))
+        assert err <= 1e-6
+
+
+def test_batch_errors():
+    A, b = _instance(1, 2, 2, 2, 12)
+    B = SemBatch(1, 16, 16, device=DEV)
+    with pytest.raises(sem.SemError):
+        B.add(A, b)  # order 12 is not batched
+    A2, b2 = _instance(2, 2, 2, 2, 3)
+    with pytest.raises(sem.SemError):
+        B.add(A2, b2, mixed=True)  # no low-precision copy
+    s = B.add(A2, b2)
+    with pytest.raises(sem.SemError):
+        A2.cg(b2)  # the context belongs to the batch
+    A3, b3 = _instance(3, 2, 2, 2, 3)
+    with pytest.raises(sem.SemError):
+        B.add(A3, b3)  # no free slot
+    with pytest.raises(sem.SemError):
+        B.set_tile(3, 5)  # tile not compiled
+    B.remove(s)
+    x, r = A2.cg(b2)
+    assert r.status == 0
