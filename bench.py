@@ -87,6 +87,122 @@ def cpu_baseline(seconds_target: float = 15.0):
     }
 
 
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def bench_batching(args, dev) -> dict:
+    """256 independent solves (log-uniform E in [64, 4096], N in {3,5,7,9,11},
+    deformed geometry, seeded right-hand sides) to 1e-8: one at a time with
+    sem_cg in FP64, then all together in one batch (FP64, and inner-outer
+    FP32 / BF16), with operator tiles from the autotuner."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+    from paper_2606_12650_amd import autotune
+    from paper_2606_12650_amd.batch import SemBatch, items_for
+
+    specs = workload.batch_instances(seed=1000, count=args.batch_instances)
+    stream = torch.cuda.Stream(device=dev)
+    res = {"instances": len(specs)}
+    with torch.cuda.stream(stream):
+        t_tune, tiles = _timed(lambda: autotune.tune(device=dev, cache_path=None))
+        res["tiles"] = {p: {str(k): v for k, v in d.items()} for p, d in tiles.items()}
+        res["autotune_s"] = t_tune
+        print(f"[bench] autotuned tiles {res['tiles']} in {t_tune:.1f} s", file=sys.stderr, flush=True)
+        ops, rhs = [], []
+        for sp in specs:
+            op = sem.SemOperator(sp["nx"], sp["ny"], sp["nz"], sp["N"], sp["amp"], lowprec="f32", device=dev)
+            ops.append(op)
+            rhs.append(workload.continuous_rhs_device(sp["rhs_seed"], sp["nx"], sp["ny"], sp["nz"], sp["N"], dev))
+        res["total_points"] = int(sum(op.L for op in ops))
+        res["total_gdof"] = int(sum(op.E * op.order ** 3 for op in ops))
+        xs = [op.empty() for op in ops]
+        # one at a time, FP64
+        def per_instance():
+            its = 0
+            for op, b, x in zip(ops, rhs, xs):
+                _, r = op.cg(b, x, rtol=1e-8)
+                its += r.iters
+            return its
+        per_instance()  # warm-up (graph capture per operator)
+        t_seq, its_seq = _timed(per_instance)
+        x_ref = [x.clone() for x in xs]
+        res["fp64_per_instance"] = {"solves_per_s": len(ops) / t_seq, "wall_s": t_seq, "iters": its_seq}
+        print(f"[bench] batching: per-instance FP64 {t_seq:.2f} s", file=sys.stderr, flush=True)
+        nop = sum(items_for(op, 1)[0] for op in ops)
+        nvec = sum(items_for(op, 1)[1] for op in ops)
+        for mode in ("fp64", "f32", "bf16"):
+            mops = ops
+            if mode == "bf16":
+                mops = [sem.SemOperator(sp["nx"], sp["ny"], sp["nz"], sp["N"], sp["amp"], lowprec="bf16",
+                                        device=dev) for sp in specs]
+            tile_prec = "f64" if mode == "fp64" else mode
+            def run_batch():
+                B = SemBatch(len(mops), nop + 64, nvec + 64, device=dev)
+                autotune.apply(B, tiles, tile_prec)
+                slots = [B.add(op, b, x, rtol=1e-8, mixed=(mode != "fp64")) for op, b, x in zip(mops, rhs, xs)]
+                out = B.run_all(iters_per_step=20)
+                for q in slots:
+                    B.remove(q)
+                B.close()
+                return out
+            run_batch()  # warm-up
+            t_b, out = _timed(run_batch)
+            ok = sum(1 for r in out.values() if r.status == 0 and r.rel_res <= 1e-8)
+            entry = {"solves_per_s": len(mops) / t_b, "wall_s": t_b, "converged": ok,
+                     "speedup_vs_fp64_per_instance": t_seq / t_b}
+            if mode == "fp64":
+                entry["bitwise_equal_to_per_instance"] = all(torch.equal(a, b) for a, b in zip(xs, x_ref))
+            else:
+                errs = []
+                for op, a, b in zip(mops, xs, x_ref):
+                    c = op.export(sem._lib.SEM_FIELD_C)
+                    errs.append(math.sqrt(float((c * (a - b) ** 2).sum()) / float((c * b ** 2).sum())))
+                entry["max_rel_err_vs_fp64"] = max(errs)
+            res[f"{mode}_batched"] = entry
+            print(f"[bench] batching: {mode} batched {entry}", file=sys.stderr, flush=True)
+            if mode == "bf16":
+                for op in mops:
+                    op.close()
+        for op in ops:
+            op.close()
+    torch.cuda.synchronize()
+    return res
+
+
+def bench_serving(args, dev) -> dict:
+    """Poisson arrivals of solve requests (log-uniform E in [64, 32768], N in
+    {5,7,9}, tolerance 1e-8, 32 GB HBM budget): continuous batching with the
+    inner-outer FP32 solver vs one FP64 sem_cg per request."""
+    import workload
+    from paper_2606_12650_amd import serve as sv
+
+    out = {}
+    n = args.serve_requests
+    for rate in [float(r) for r in args.serve_rates.split(",") if r]:
+        specs = workload.serving_requests(5, n)
+        reqs = sv.make_requests(specs, workload.poisson_arrivals(5, rate, n))
+        st_b, _ = sv.serve(reqs, dev, mixed="f32", hbm_budget=32 << 30, max_slots=64, iters_per_step=20)
+        sb = st_b.summary()
+        st_p = sv.serve_per_request(reqs, dev)
+        sp = st_p.summary()
+        out[str(int(rate))] = {"mixed_f32_continuous_batching": sb, "fp64_per_request": sp,
+                               "solves_per_s_ratio": sb["solves_per_s"] / max(sp["solves_per_s"], 1e-12)}
+        print(f"[bench] serving rate {rate}: batched {sb['solves_per_s']:.1f}/s p99 {sb['p99_latency_s']:.2f}s, "
+              f"per-request {sp['solves_per_s']:.1f}/s p99 {sp['p99_latency_s']:.2f}s", file=sys.stderr, flush=True)
+    out["requests_per_rate"] = n
+    out["mesh_mix"] = "E log-uniform [64, 32768], N uniform {5,7,9}, amp 0.05, tol 1e-8"
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +210,11 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--ax-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true", help="skip the 256-instance batching study")
+    ap.add_argument("--skip-serve", action="store_true", help="skip the serving study")
+    ap.add_argument("--batch-instances", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-rates", type=str, default="50,1000")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -220,6 +341,9 @@ def main(argv=None) -> int:
             del Am, xm
         torch.cuda.synchronize()
 
+    batching = None if args.skip_batch else bench_batching(args, dev)
+    serving = None if args.skip_serve else bench_serving(args, dev)
+
     E, L = A.E, A.L
     gdof = E * N ** 3
     value = gdof * timed_iters / wall / 1e9
@@ -271,6 +395,10 @@ def main(argv=None) -> int:
             "kernel_source_hash": khash,
         },
     }
+    if batching is not None:
+        out["batching"] = batching
+    if serving is not None:
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

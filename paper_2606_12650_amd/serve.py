@@ -1,0 +1,270 @@
+"""Serving form: continuous batching of Poisson-arrival solve requests.
+
+Requests (a box mesh, an order, a seeded right-hand side) arrive over time.
+The scheduler admits them first-come first-served while a batch slot is free
+and their device footprint (``sem_workspace_bytes`` plus b and x) fits the
+HBM budget; every step advances all admitted solves by a few CG iterations in
+one batched launch sequence; finished solves leave at once and free their
+slot and memory for the next request.  Requests that arrive while others are
+on the GPU therefore join the running batch (iteration-level continuous
+batching), not a queue behind it.
+
+The policy (:class:`Scheduler`) is separate from the device work
+(:class:`GpuExecutor`) so that it can be exercised with a simulated clock.
+The baseline :func:`serve_per_request` solves one request at a time with
+``sem_cg`` in FP64.
+"""
+
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    index: int
+    nx: int
+    ny: int
+    nz: int
+    N: int
+    amp: float
+    rhs_seed: int
+    arrival: float  # seconds from the start of the run
+
+    @property
+    def E(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def L(self) -> int:
+        return self.E * (self.N + 1) ** 3
+
+
+@dataclass
+class Completion:
+    index: int
+    arrival: float
+    admitted: float
+    finished: float
+    iters: int
+    outer_iters: int
+    status: int
+    rel_res: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+@dataclass
+class ServeStats:
+    completions: list = field(default_factory=list)
+    rejected: list = field(default_factory=list)
+    wall: float = 0.0
+    max_active: int = 0
+    peak_bytes: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array([c.latency for c in self.completions]) if self.completions else np.zeros(1)
+        ok = sum(1 for c in self.completions if c.status == 0)
+        return {
+            "requests": len(self.completions) + len(self.rejected),
+            "completed": len(self.completions),
+            "converged": ok,
+            "rejected": len(self.rejected),
+            "solves_per_s": ok / self.wall if self.wall > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()),
+            "wall_s": self.wall,
+            "max_active": self.max_active,
+            "peak_bytes": self.peak_bytes,
+        }
+
+
+def make_requests(specs: list[dict], arrivals) -> list[Request]:
+    return [Request(s["index"], s["nx"], s["ny"], s["nz"], s["N"], s["amp"], s["rhs_seed"], float(t))
+            for s, t in zip(specs, arrivals)]
+
+
+class Scheduler:
+    """First-come first-served admission by free slot and HBM budget, with
+    iteration-level continuous batching.
+
+    ``executor`` provides ``footprint(req)``, ``admit(req) -> slot``,
+    ``step()``, ``poll() -> [(slot, result)]``, ``release(slot)`` and
+    ``active``; ``clock()`` returns seconds since the start and
+    ``sleep(dt)`` waits (both injectable for tests).
+    """
+
+    def __init__(self, executor, hbm_budget: int, max_slots: int, clock=None, sleep=None):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        t0 = time.perf_counter()
+        self.clock = clock or (lambda: time.perf_counter() - t0)
+        self.sleep = sleep or time.sleep
+
+    def run(self, requests: list[Request]) -> ServeStats:
+        stats = ServeStats()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        queue: deque = deque()
+        active: dict = {}  # slot -> (request, footprint, admitted time)
+        used = 0
+        start = self.clock()
+        while pending or queue or active:
+            now = self.clock()
+            while pending and pending[0].arrival <= now - start:
+                queue.append(pending.popleft())
+            while queue and len(active) < self.max_slots:
+                req = queue[0]
+                fp = self.ex.footprint(req)
+                if fp > self.budget:  # can never fit: refuse rather than block the queue
+                    queue.popleft()
+                    stats.rejected.append(req.index)
+                    continue
+                if used + fp > self.budget:
+                    break
+                queue.popleft()
+                slot = self.ex.admit(req)
+                active[slot] = (req, fp, self.clock() - start)
+                used += fp
+                stats.peak_bytes = max(stats.peak_bytes, used)
+            stats.max_active = max(stats.max_active, len(active))
+            if active:
+                self.ex.step()
+                done = self.ex.poll()
+                tnow = self.clock() - start
+                for slot, res in done:
+                    req, fp, adm = active.pop(slot)
+                    self.ex.release(slot)
+                    used -= fp
+                    stats.completions.append(Completion(req.index, req.arrival, adm, tnow, res.iters,
+                                                        res.outer_iters, res.status, res.rel_res))
+            elif pending:
+                wait = pending[0].arrival - (self.clock() - start)
+                if wait > 0:
+                    self.sleep(wait)
+        stats.wall = self.clock() - start
+        return stats
+
+
+class GpuExecutor:
+    """Device side of the scheduler: one SemBatch; each admitted request gets
+    its own SemOperator (set up on the GPU) and a right-hand side drawn on
+    the GPU from its seed."""
+
+    def __init__(self, device="cuda", max_slots=64, mixed: str | None = "f32", iters_per_step=10,
+                 max_op_items=1 << 20, max_vec_items=1 << 18, tiles: dict | None = None,
+                 rtol=1e-8, keep_solutions=False):
+        import torch
+
+        from .batch import SemBatch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.mixed = mixed
+        self.iters = int(iters_per_step)
+        self.rtol = rtol
+        self.batch = SemBatch(max_slots, max_op_items, max_vec_items, device=self.device)
+        for order, epb in (tiles or {}).items():
+            self.batch.set_tile(int(order), int(epb))
+        self.slots: dict = {}
+        self.keep = keep_solutions
+        self.solutions: dict = {}  # request index -> x (when keep_solutions)
+
+    def footprint(self, req: Request) -> int:
+        from .sem import workspace_bytes
+
+        return workspace_bytes(req.nx, req.ny, req.nz, req.N, req.amp, self.mixed) + 16 * req.L + 512
+
+    def admit(self, req: Request) -> int:
+        import workload
+
+        from .sem import SemOperator
+
+        op = SemOperator(req.nx, req.ny, req.nz, req.N, req.amp, lowprec=self.mixed, device=self.device)
+        b = workload.continuous_rhs_device(req.rhs_seed, req.nx, req.ny, req.nz, req.N, self.device)
+        slot = self.batch.add(op, b, rtol=self.rtol, mixed=self.mixed is not None)
+        self.slots[slot] = req
+        return slot
+
+    def step(self) -> None:
+        self.batch.step(self.iters)
+
+    def poll(self):
+        fin, _ = self.batch.poll()
+        return fin
+
+    def release(self, slot: int):
+        op, b, x = self.batch.remove(slot)
+        req = self.slots.pop(slot, None)
+        op.close()
+        if self.keep and req is not None:
+            self.solutions[req.index] = x
+        return x
+
+    @property
+    def active(self) -> int:
+        return len(self.slots)
+
+
+def serve_per_request(requests: list[Request], device="cuda", rtol=1e-8, clock=None,
+                      sleep=None) -> ServeStats:
+    """Baseline: one request at a time, FP64 ``sem_cg``, in arrival order."""
+    import torch
+
+    import workload
+
+    from .sem import SemOperator
+
+    t0 = time.perf_counter()
+    clock = clock or (lambda: time.perf_counter() - t0)
+    sleep = sleep or time.sleep
+    stats = ServeStats()
+    dev = torch.device(device)
+    stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(stream):
+        start = clock()
+        for req in sorted(requests, key=lambda r: r.arrival):
+            wait = req.arrival - (clock() - start)
+            if wait > 0:
+                sleep(wait)
+            adm = clock() - start
+            op = SemOperator(req.nx, req.ny, req.nz, req.N, req.amp, device=dev)
+            b = workload.continuous_rhs_device(req.rhs_seed, req.nx, req.ny, req.nz, req.N, dev)
+            _, res = op.cg(b, rtol=rtol, raise_on_fail=False)
+            op.close()
+            stats.completions.append(Completion(req.index, req.arrival, adm, clock() - start, res.iters,
+                                                res.outer_iters, res.status, res.rel_res))
+            stats.max_active = 1
+        stats.wall = clock() - start
+    torch.cuda.synchronize(dev)
+    return stats
+
+
+def serve(requests: list[Request], device="cuda", mixed: str | None = "f32", hbm_budget=32 << 30,
+          max_slots=64, iters_per_step=10, tiles: dict | None = None, rtol=1e-8,
+          keep_solutions=False):
+    """Run the continuous-batching server over ``requests`` on one GPU, on a
+    stream of its own (so that each batched step replays as one graph).
+    Returns (ServeStats, {request index: x} or {})."""
+    import torch
+
+    dev = torch.device(device)
+    stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(stream):
+        ex = GpuExecutor(dev, max_slots=max_slots, mixed=mixed, iters_per_step=iters_per_step,
+                         tiles=tiles, rtol=rtol, keep_solutions=keep_solutions)
+        try:
+            stats = Scheduler(ex, hbm_budget, max_slots).run(requests)
+        finally:
+            ex.batch.close()
+    torch.cuda.synchronize(dev)
+    return stats, ex.solutions

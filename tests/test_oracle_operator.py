@@ -288,3 +288,14 @@ def test_patch_equals_full_mesh(center):
     for mode, ref in (("masked", pr.ax(u)), ("local", pr.ax_local(u)),
                       ("assembled", pr.ax_assembled(u))):
         assert np.array_equal(P.ax_center(up, mode), ref[center])
+
+
+def test_lattice_layout_matches_element_loop():
+    """The input generator's strided copy puts lattice node (ex*N+i, ey*N+j,
+    ez*N+k) at element ex + nx(ey + ny ez), local (i, j, k)."""
+    nx, ny, nz, N = 3, 2, 4, 3
+    g = workload.random_lattice(3, nx, ny, nz, N, zero_boundary=False)
+    lv = workload.lattice_to_lvector(g, nx, ny, nz, N)
+    from oracle.mesh import lattice_indices
+    I, J, K = lattice_indices(nx, ny, nz, N)
+    assert np.array_equal(lv, g[K, J, I])

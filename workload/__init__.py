@@ -46,12 +46,9 @@ def lattice_to_lvector(grid: np.ndarray, nx: int, ny: int, nz: int, N: int) -> n
     ``(E, N+1, N+1, N+1)`` with ``out[e, k, j, i] = grid[ez*N+k, ey*N+j, ex*N+i]``.
     """
     n = N + 1
-    out = np.empty((nz, ny, nx, n, n, n), dtype=grid.dtype)
-    for ez in range(nz):
-        for ey in range(ny):
-            for ex in range(nx):
-                out[ez, ey, ex] = grid[ez * N:ez * N + n, ey * N:ey * N + n, ex * N:ex * N + n]
-    return out.reshape(nx * ny * nz, n, n, n)
+    win = np.lib.stride_tricks.sliding_window_view(grid, (n, n, n))[::N, ::N, ::N]
+    assert win.shape == (nz, ny, nx, n, n, n)
+    return np.ascontiguousarray(win).reshape(nx * ny * nz, n, n, n)
 
 
 def random_lattice(seed: int, nx: int, ny: int, nz: int, N: int, zero_boundary: bool = True) -> np.ndarray:
@@ -138,3 +135,24 @@ def serving_requests(seed: int, count: int, e_lo: int = 64, e_hi: int = 32768,
         out.append(dict(index=i, nx=nx, ny=ny, nz=nz, N=N, amp=amp,
                         rhs_seed=int(seed) * 100003 + i))
     return out
+
+
+def continuous_rhs_device(seed: int, nx: int, ny: int, nz: int, N: int, device, zero_boundary: bool = True):
+    """A continuous right-hand side drawn on the GPU (for serving, where a
+    request's data must not wait on the host): uniform[-1,1] per lattice node
+    from torch's Philox generator seeded with ``seed``, zero on the box faces,
+    copied into element-local layout by a strided window view.  Returns a
+    float64 CUDA tensor of length L."""
+    import torch
+
+    n = N + 1
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    g = torch.rand(lattice_shape(nx, ny, nz, N), generator=gen, device=device, dtype=torch.float64)
+    g = g * 2.0 - 1.0
+    if zero_boundary:
+        g[0], g[-1] = 0.0, 0.0
+        g[:, 0], g[:, -1] = 0.0, 0.0
+        g[:, :, 0], g[:, :, -1] = 0.0, 0.0
+    win = g.unfold(0, n, N).unfold(1, n, N).unfold(2, n, N)  # (nz, ny, nx, k, j, i)
+    return win.contiguous().reshape(-1)
