@@ -34,7 +34,7 @@ METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latenc
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_internal.h", "sem_device.h"):
+    for f in ("sem_ax.hip", "sem_ax_tile.h", "sem_internal.h", "sem_device.h"):
         with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -203,6 +203,56 @@ def bench_serving(args, dev) -> dict:
     return out
 
 
+def _box_for(E: int):
+    """Balanced power-of-two box with E = 2^p elements."""
+    p = int(round(math.log2(E)))
+    dims = [1, 1, 1]
+    for q in range(p):
+        dims[q % 3] *= 2
+    return dims[0], dims[1], dims[2]
+
+
+def sweep(args) -> int:
+    """GDOFS vs number of DOFs (the paper's Sec. VIII-B study, Eq. gdofs),
+    re-run on one MI355X with this library's Jacobi-PCG (FP64, deformed box):
+    for each N and E = 2^1..2^14, 100 warm-up iterations, then 100 timed
+    iterations, averaged over 5 runs.  One JSON line per (N, E), then one
+    summary line."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(device=dev)
+    rows = []
+    with torch.cuda.stream(stream):
+        for N in (4, 6, 8):
+            for p in range(1, 15):
+                nx, ny, nz = _box_for(2 ** p)
+                A = sem.SemOperator(nx, ny, nz, N, 0.05, device=dev)
+                b = torch.from_numpy(workload.continuous_rhs(4, nx, ny, nz, N)).to(dev)
+                x = torch.empty_like(b)
+                A.cg(b, x, fixed_iter=100, check_every=100)  # warm-up (and graph capture)
+                times = []
+                for _ in range(5):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, res = A.cg(b, x, fixed_iter=100, check_every=100)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                t = sum(times) / len(times)
+                E = nx * ny * nz
+                row = {"N": N, "E": E, "dofs": E * N ** 3, "unique_dofs": (nx * N + 1) * (ny * N + 1) * (nz * N + 1),
+                       "t_100_iters_s": t, "gdofs": E * N ** 3 * 100 / t / 1e9, "rel_res": res.rel_res}
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+                A.close()
+    best = {N: max(r["gdofs"] for r in rows if r["N"] == N) for N in (4, 6, 8)}
+    print(json.dumps({"sweep": "gdofs_vs_dofs", "max_gdofs": best}), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +265,12 @@ def main(argv=None) -> int:
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-rates", type=str, default="50,1000")
+    ap.add_argument("--sweep", action="store_true",
+                    help="the paper's study instead: GDOF/s vs DOFs for N = 4, 6, 8, E = 2^1..2^14, "
+                         "100 warm-up + 100 timed PCG iterations, mean of 5 runs")
     args = ap.parse_args(argv)
+    if args.sweep and args.gpus == 1:
+        return sweep(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the path is single-GPU; see the sharding notes in the design document)",
@@ -312,8 +367,23 @@ def main(argv=None) -> int:
         mixed = {}
         x64 = x.clone()
         c_w = A.export(sem._lib.SEM_FIELD_C)
-        for prec in ("f32", "bf16"):
-            Am = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=dev)
+        for prec, mf in (("f32", False), ("f32", True), ("bf16", False), ("bf16", True)):
+            key = prec + ("_mfma" if mf else "")
+            Am = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=dev, mfma=mf)
+            # the low-precision element operator alone (one launch, FP32 in/out)
+            u32 = u.to(torch.float32)
+            w32 = torch.empty_like(u32)
+            for _ in range(3):
+                Am.ax_lowp(u32, sem.LOCAL, out=w32)
+            l0 = torch.cuda.Event(enable_timing=True)
+            l1 = torch.cuda.Event(enable_timing=True)
+            l0.record(stream)
+            for _ in range(args.ax_reps):
+                Am.ax_lowp(u32, sem.LOCAL, out=w32)
+            l1.record(stream)
+            torch.cuda.synchronize()
+            lowp_ax_us = l0.elapsed_time(l1) * 1e3 / args.ax_reps
+            del u32, w32
             xm = torch.empty_like(b)
             for _ in range(max(1, args.warmup)):
                 Am.cg(b, xm, rtol=rtol, mixed=True)
@@ -328,7 +398,10 @@ def main(argv=None) -> int:
             torch.cuda.synchronize()
             wm = time.perf_counter() - t0m
             err = math.sqrt(float((c_w * (xm - x64) ** 2).sum()) / float((c_w * x64 ** 2).sum()))
-            mixed[prec] = {
+            mixed[key] = {
+                "contractions": "mfma" if mf else "valu",
+                "ax_local_us": lowp_ax_us,
+                "ax_local_gdofs": A.E * N ** 3 / lowp_ax_us / 1e3,
                 "solves_per_s": msteps / wm,
                 "ms_per_solve": wm / msteps * 1e3,
                 "inner_iters_per_solve": inner / msteps,
@@ -337,7 +410,7 @@ def main(argv=None) -> int:
                 "rel_err_vs_fp64_solution": err,
                 "status": rm.status,
             }
-            print(f"[bench] mixed {prec}: {mixed[prec]}", file=sys.stderr, flush=True)
+            print(f"[bench] mixed {key}: {mixed[key]}", file=sys.stderr, flush=True)
             del Am, xm
         torch.cuda.synchronize()
 

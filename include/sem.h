@@ -80,8 +80,12 @@ typedef struct {
   int32_t lowprec;          /* SEM_F64 (none), SEM_F32 or SEM_BF16: also keep a
                                rounded copy of G for the inner solver of the
                                mixed-precision CG                              */
-  int32_t reserved;         /* must be 0                                        */
+  int32_t flags;            /* 0, or SEM_FLAG_MFMA: the low-precision copy's D
+                               contractions run on the matrix cores (MFMA,
+                               FP32 accumulation) instead of the vector ALUs */
 } sem_mesh_desc;
+
+enum { SEM_FLAG_MFMA = 1 };
 
 /* Device bytes sem_setup needs for this mesh (0 if the descriptor is invalid).
  * It covers G, the Jacobi diagonal, D, the CG vectors and reduction scratch;

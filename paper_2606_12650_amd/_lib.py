@@ -22,6 +22,7 @@ SEM_ERR_UNSUPPORTED = -6
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_AX_LOCAL, SEM_AX_ASSEMBLED, SEM_AX_MASKED = 0, 1, 3
 SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2, 3, 4
+SEM_FLAG_MFMA = 1
 
 # Every symbol include/sem.h declares.
 EXPORTS = (
@@ -35,7 +36,7 @@ EXPORTS = (
 class SemMeshDesc(ctypes.Structure):
     _fields_ = [("nelx", ctypes.c_int32), ("nely", ctypes.c_int32), ("nelz", ctypes.c_int32),
                 ("order", ctypes.c_int32), ("deform_amp", ctypes.c_double),
-                ("lowprec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lowprec", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class SemCgOpts(ctypes.Structure):

@@ -57,7 +57,11 @@ bool desc_valid(const sem_mesh_desc *d, std::string *why) {
     *why = "lowprec must be SEM_F64, SEM_F32 or SEM_BF16";
     return false;
   }
-  if (d->reserved != 0) { *why = "reserved field must be 0"; return false; }
+  if (d->flags != 0 && d->flags != SEM_FLAG_MFMA) { *why = "flags must be 0 or SEM_FLAG_MFMA"; return false; }
+  if (d->flags == SEM_FLAG_MFMA && d->lowprec == SEM_F64) {
+    *why = "SEM_FLAG_MFMA needs a low-precision copy (lowprec SEM_F32 or SEM_BF16)";
+    return false;
+  }
   if (!std::isfinite(d->deform_amp)) { *why = "deform_amp must be finite"; return false; }
   const double L = (double)d->nelx * d->nely * d->nelz * std::pow(d->order + 1.0, 3);
   if (L > 4.0e9) { *why = "mesh too large (L > 4e9)"; return false; }
@@ -215,8 +219,8 @@ int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
 // on FP32 vectors with the rounded operator; the inner correction e plays x.
 int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->Dlo, c->Glo, c->pin, c->win, c->rin, c->minv32,
-                               c->e, c->st_in, c->part_ax, s));
+  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->desc.flags & SEM_FLAG_MFMA, c->Dlo, c->Glo,
+                               c->pin, c->win, c->rin, c->minv32, c->e, c->st_in, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
   SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_vec_blocks, s));
@@ -509,8 +513,9 @@ int sem_ax_lowp(sem_ctx *ctx, const float *u, float *w, int mode, void *stream) 
     return fail(SEM_ERR_ARG, "sem_ax_lowp: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
   float *dst = mode == SEM_AX_LOCAL ? w : ctx->win;
-  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->Dlo, ctx->Glo, const_cast<float *>(u),
-                               dst, nullptr, nullptr, nullptr, nullptr, nullptr, s));
+  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->desc.flags & SEM_FLAG_MFMA, ctx->Dlo,
+                               ctx->Glo, const_cast<float *>(u), dst, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, s));
   if (mode != SEM_AX_LOCAL)
     SEM_HIP(semk::launch_gather_f32(ctx->box, ctx->win, w,
                                     mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));

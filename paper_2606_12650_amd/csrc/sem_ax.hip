@@ -9,6 +9,7 @@
 // of the element (element-major layout, i fastest).
 #include <hip/hip_runtime.h>
 
+#include "sem_ax_mfma.h"
 #include "sem_ax_tile.h"
 #include "sem_device.h"
 #include "sem_internal.h"
@@ -49,6 +50,34 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
   }
   ax_tile<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha, beta,
                              part, sD, s1, s2, s3, sred);
+}
+
+// The low-precision operator with the D contractions on the matrix cores:
+// the per-order tile of ax_kernel, rounded up to whole waves.
+template <int N1>
+struct MfmaCfg {
+  static constexpr int EPB = AxCfg<N1>::EPB;
+  static constexpr int THREADS = (N1 * N1 * EPB + 63) / 64 * 64;
+};
+
+template <int N1, class P, bool CG>
+__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS)
+    ax_mfma_kernel(int64_t E, const float *__restrict__ Dg, const typename P::TG *__restrict__ G,
+                   float *u, float *__restrict__ w, const float *__restrict__ r,
+                   const float *__restrict__ minv, float *__restrict__ x, CgState *__restrict__ st,
+                   double *__restrict__ part) {
+  using C = MfmaCfg<N1>;
+  __shared__ float sD[N1 * N1];
+  __shared__ float tiles[MfmaTile<N1>::kTiles * C::EPB * AxTile<N1>::TILE];
+  __shared__ double sred[CG ? C::THREADS : 1];
+  double alpha = 0.0, beta = 0.0;
+  if (CG) {
+    if (st->done) return;
+    alpha = st->alpha;
+    beta = st->beta;
+  }
+  ax_tile_mfma<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha,
+                                  beta, part, sD, tiles, sred);
 }
 
 // Rounded copy of G for a low-precision operator.
@@ -205,6 +234,23 @@ hipError_t ax_dispatch(const Box &b, const void *D, const void *G, void *u, void
   return hipGetLastError();
 }
 
+template <int N1, class P>
+hipError_t mfma_dispatch(const Box &b, const float *D, const void *G, float *u, float *w,
+                         const float *r, const float *minv, float *x, CgState *cg, double *part,
+                         hipStream_t s) {
+  using C = MfmaCfg<N1>;
+  using TG = typename P::TG;
+  const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
+  if (blocks == 0) return hipSuccess;
+  if (cg)
+    hipLaunchKernelGGL((ax_mfma_kernel<N1, P, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       b.E(), D, (const TG *)G, u, w, r, minv, x, cg, part);
+  else
+    hipLaunchKernelGGL((ax_mfma_kernel<N1, P, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
+                       s, b.E(), D, (const TG *)G, u, w, r, minv, x, cg, part);
+  return hipGetLastError();
+}
+
 template <int N1>
 hipError_t setup_dispatch(const Box &b, double amp, const double *D, const double *nodes,
                           double *G, double *diag, hipStream_t s) {
@@ -252,9 +298,31 @@ hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double 
   }
 }
 
-hipError_t launch_ax_lowp(const Box &b, int prec, const float *D, const void *G, float *u, float *w,
-                          const float *r, const float *minv, float *x, CgState *cg, double *part,
-                          hipStream_t s) {
+hipError_t launch_ax_lowp(const Box &b, int prec, int mfma, const float *D, const void *G, float *u,
+                          float *w, const float *r, const float *minv, float *x, CgState *cg,
+                          double *part, hipStream_t s) {
+  if (mfma && prec == SEM_F32) {
+    switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return mfma_dispatch<n + 1, PrecF32>(b, D, G, u, w, r, minv, x, cg, part, s);
+      SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  if (mfma && prec == SEM_BF16) {
+    switch (b.N) {
+#define CASE(n) \
+  case n:       \
+    return mfma_dispatch<n + 1, PrecBF16>(b, D, G, u, w, r, minv, x, cg, part, s);
+      SEM_FOR_EACH_ORDER(CASE)
+#undef CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
   if (prec == SEM_F32) {
     switch (b.N) {
 #define CASE(n) \

@@ -167,10 +167,10 @@ hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double 
 // Low-precision operator (prec SEM_F32 or SEM_BF16): FP32 vectors, G stored
 // as float or bfloat16 bits, D as float (bfloat16-rounded in BF16 mode),
 // FP32 accumulation; the CG variant mirrors launch_ax_f64 (x is the inner
-// correction e).
-hipError_t launch_ax_lowp(const Box &b, int prec, const float *D, const void *G, float *u, float *w,
-                          const float *r, const float *minv, float *x, CgState *cg, double *part,
-                          hipStream_t s);
+// correction e).  mfma != 0: the D contractions on the matrix cores.
+hipError_t launch_ax_lowp(const Box &b, int prec, int mfma, const float *D, const void *G, float *u,
+                          float *w, const float *r, const float *minv, float *x, CgState *cg,
+                          double *part, hipStream_t s);
 // dst[i] = src[i] rounded to float (SEM_F32) or to bfloat16 bits (SEM_BF16).
 hipError_t launch_convert_g(int prec, int64_t n, const double *src, void *dst, hipStream_t s);
 

@@ -44,27 +44,27 @@ class CgResult:
     rel_res: float
 
 
-def mesh_desc(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None) -> L.SemMeshDesc:
+def mesh_desc(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=False) -> L.SemMeshDesc:
     return L.SemMeshDesc(int(nelx), int(nely), int(nelz), int(order), float(deform_amp),
-                         _PREC[lowprec], 0)
+                         _PREC[lowprec], L.SEM_FLAG_MFMA if mfma else 0)
 
 
-def workspace_bytes(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None) -> int:
-    d = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec)
+def workspace_bytes(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=False) -> int:
+    d = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec, mfma)
     return int(L.lib().sem_workspace_bytes(ctypes.byref(d)))
 
 
 class SemOperator:
     """The Poisson operator of one box mesh, set up on the GPU (``sem_setup``)."""
 
-    def __init__(self, nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, device="cuda"):
+    def __init__(self, nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, device="cuda", mfma=False):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("SemOperator needs a CUDA (HIP) device")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         lib = L.lib()
-        self.desc = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec)
+        self.desc = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec, mfma)
         nbytes = int(lib.sem_workspace_bytes(ctypes.byref(self.desc)))
         if nbytes == 0:
             raise ValueError(f"invalid mesh descriptor {nelx}x{nely}x{nelz} N={order}")

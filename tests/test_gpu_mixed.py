@@ -16,6 +16,7 @@ Inner-outer CG: the solve reports an FP64 true residual <= rtol, and
 
 import math
 import os
+import types
 
 import numpy as np
 import pytest
@@ -45,12 +46,13 @@ def _tol(prec, N):
     return (4 * (N + 1) + 8) * 2.0 ** -24 if prec == "f32" else 2.0 ** -7
 
 
+@pytest.mark.parametrize("mfma", [False, True], ids=["valu", "mfma"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 11, 12])
-def test_lowp_operator_componentwise(prec, N):
+def test_lowp_operator_componentwise(prec, N, mfma):
     nx, ny, nz, amp = 3, 2, 2, 0.05
     pr = op.Problem(nx, ny, nz, N, amp)
-    A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=DEV, mfma=mfma)
     u = workload.iid_lvector(300 + N, pr.L).astype(np.float32).astype(np.float64)
     ug = torch.from_numpy(u.astype(np.float32)).to(DEV)
     ref = ax_local_rounded(pr, u, prec)
@@ -67,18 +69,19 @@ def test_lowp_operator_componentwise(prec, N):
     # the error against the FP64 operator, stated
     exact = pr.ax_local(u)
     rel = float(np.max(np.abs(w - exact)) / np.max(np.abs(exact)))
-    print(f"[lowp] {prec} N={N}: max|A_lo u - A u| / max|A u| = {rel:.3e}")
+    print(f"[lowp] {prec} mfma={mfma} N={N}: max|A_lo u - A u| / max|A u| = {rel:.3e}")
     assert rel < (1e-5 if prec == "f32" else 5e-2)
 
 
+@pytest.mark.parametrize("mfma", [False, True], ids=["valu", "mfma"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("mesh,N", [((3, 3, 3), 5), ((4, 3, 2), 7), ((2, 2, 3), 11)])
-def test_mixed_cg_small(prec, mesh, N):
+def test_mixed_cg_small(prec, mesh, N, mfma):
     nx, ny, nz = mesh
     pr = op.Problem(nx, ny, nz, N, 0.05)
     b = workload.continuous_rhs(40 + N, nx, ny, nz, N)
     xr, _ = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, rtol=1e-12)
-    A = sem.SemOperator(nx, ny, nz, N, 0.05, lowprec=prec, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, 0.05, lowprec=prec, device=DEV, mfma=mfma)
     bg = torch.from_numpy(b).to(DEV)
     x, res = A.cg(bg, rtol=1e-8, mixed=True, inner_rtol=1e-3)
     assert res.status == 0 and res.rel_res <= 1e-8 and res.outer_iters >= 2
@@ -116,6 +119,29 @@ def test_mixed_requires_lowprec_copy():
         A.cg(bg, rtol=1e-8, mixed=True)
     with pytest.raises(sem.SemError):
         A.ax_lowp(torch.zeros(A.L, dtype=torch.float32, device=DEV))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mfma_operator_full_size_sampled(prec):
+    """32x32x32 deformed N = 7 with the contractions on the matrix cores: on a
+    sample of elements, the local result is inside the componentwise bound of
+    the rounded operator evaluated by the oracle on a 27-element patch."""
+    nx = ny = nz = 32
+    N, amp = 7, 0.05
+    A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=DEV, mfma=True)
+    u = workload.iid_lvector(77, A.L).astype(np.float32)
+    w = A.ax_lowp(torch.from_numpy(u).to(DEV), sem.LOCAL).cpu().numpy().astype(np.float64)
+    n3 = (N + 1) ** 3
+    rng = np.random.default_rng(5)
+    for e in [int(v) for v in rng.integers(0, A.E, size=6)] + [0, A.E - 1]:
+        pe = op.Patch(nx, ny, nz, N, amp, e)
+        els = np.asarray(pe.elements)
+        ue = u.astype(np.float64)[els[:, None] * n3 + np.arange(n3)].reshape(-1)
+        local = types.SimpleNamespace(D=pe.D, G=pe.G, shape4=lambda v: v.reshape(-1, N + 1, N + 1, N + 1))
+        ref = ax_local_rounded(local, ue, prec).reshape(len(els), -1)[pe.center_slot]
+        B = ax_local_abs_bound(local, ue, prec).reshape(len(els), -1)[pe.center_slot]
+        got = w[e * n3:(e + 1) * n3]
+        assert np.all(np.abs(got - ref) <= _tol(prec, N) * B + 1e-30), e
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
