@@ -136,15 +136,15 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         const int64_t idx = base + k * PL;
-        const float pold = u[idx];
-        x[idx] += alpha * pold;
-        const float v = minv[idx] * r[idx] + beta * pold;
+        const float pold = ld_once(u + idx);
+        st_once(x + idx, ld_once(x + idx) + alpha * pold);
+        const float v = ld_once(minv + idx) * ld_once(r + idx) + beta * pold;
         uk[k] = v;
-        u[idx] = v;
+        st_once(u + idx, v);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < N1; ++k) uk[k] = u[base + k * PL];
+      for (int k = 0; k < N1; ++k) uk[k] = ld_once(u + base + k * PL);
     }
   } else {
 #pragma unroll

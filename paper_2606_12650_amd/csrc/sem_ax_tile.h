@@ -70,15 +70,15 @@ __device__ __forceinline__ void ax_tile(int64_t E, int64_t e0, const typename P:
 #pragma unroll
       for (int k = 0; k < N1; ++k) {
         const int64_t idx = base + k * PL;
-        const TV pold = u[idx];
-        x[idx] += alpha * pold;
-        const TV v = minv[idx] * r[idx] + beta * pold;
+        const TV pold = ld_once(u + idx);
+        st_once(x + idx, ld_once(x + idx) + alpha * pold);
+        const TV v = ld_once(minv + idx) * ld_once(r + idx) + beta * pold;
         uk[k] = (TC)v;
-        u[idx] = v;
+        st_once(u + idx, v);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < N1; ++k) uk[k] = (TC)u[base + k * PL];
+      for (int k = 0; k < N1; ++k) uk[k] = (TC)ld_once(u + base + k * PL);
     }
     if constexpr (kPrefetchG) {
 #pragma unroll

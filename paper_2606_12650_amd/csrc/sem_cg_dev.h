@@ -65,12 +65,12 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t L, int64_t tile,
       const Node<N1> n = node_at<N1>(b, idx);
       if (!n.boundary) {
         const double wa = gather_copies<N1>(w, b, n, idx);
-        const TV rt = (TV)((double)r[idx] - alpha * wa);
+        const TV rt = (TV)((double)ld_once(r + idx) - alpha * wa);
         r[idx] = rt;
         const double rv = (double)rt;
         const double c = 1.0 / (double)n.mult;
         rr += c * rv * rv;
-        rz += c * rv * ((double)minv[idx] * rv);
+        rz += c * rv * ((double)ld_once(minv + idx) * rv);
       }
     }
   }

@@ -58,12 +58,17 @@ def test_served_equals_alone(mixed):
 def test_budget_caps_admission():
     specs = workload.serving_requests(12, 10, e_lo=8, e_hi=64, orders=(5,))
     reqs = make_requests(specs, [0.0] * 10)
-    # a budget that holds about two requests at a time
+    # a budget that holds the largest request beside the smallest, far less
+    # than all ten together: admission must wait for memory, never exceed it
     from paper_2606_12650_amd.sem import workspace_bytes
-    one = max(workspace_bytes(r.nx, r.ny, r.nz, r.N, r.amp, "f32") + 16 * r.L + 512 for r in reqs)
-    stats, _ = serve(reqs, DEV, mixed="f32", hbm_budget=2 * one + 1, max_slots=8, iters_per_step=5)
+    fp = [workspace_bytes(r.nx, r.ny, r.nz, r.N, r.amp, "f32") + 16 * r.L + 512 for r in reqs]
+    budget = max(fp) + min(fp)
+    assert sum(fp) > budget
+    stats, _ = serve(reqs, DEV, mixed="f32", hbm_budget=budget, max_slots=8, iters_per_step=5)
     s = stats.summary()
-    assert s["converged"] == 10 and s["max_active"] <= 2 and s["peak_bytes"] <= 2 * one + 1
+    print(f"[serve] budget {budget}: {s}")
+    assert s["converged"] == 10 and s["rejected"] == 0
+    assert s["peak_bytes"] <= budget and 1 <= s["max_active"] < 10
 
 
 def test_per_request_baseline_runs():
