@@ -107,7 +107,7 @@ def bench_batching(args, dev) -> dict:
     import workload
     import paper_2606_12650_amd as sem
     from paper_2606_12650_amd import autotune
-    from paper_2606_12650_amd.batch import SemBatch, items_for
+    from paper_2606_12650_amd.batch import SemBatch
 
     specs = workload.batch_instances(seed=1000, count=args.batch_instances)
     stream = torch.cuda.Stream(device=dev)
@@ -137,8 +137,6 @@ def bench_batching(args, dev) -> dict:
         x_ref = [x.clone() for x in xs]
         res["fp64_per_instance"] = {"solves_per_s": len(ops) / t_seq, "wall_s": t_seq, "iters": its_seq}
         print(f"[bench] batching: per-instance FP64 {t_seq:.2f} s", file=sys.stderr, flush=True)
-        nop = sum(items_for(op, 1)[0] for op in ops)
-        nvec = sum(items_for(op, 1)[1] for op in ops)
         for mode in ("fp64", "f32", "bf16"):
             mops = ops
             if mode == "bf16":
@@ -146,7 +144,7 @@ def bench_batching(args, dev) -> dict:
                                         device=dev) for sp in specs]
             tile_prec = "f64" if mode == "fp64" else mode
             def run_batch():
-                B = SemBatch(len(mops), nop + 64, nvec + 64, device=dev)
+                B = SemBatch(len(mops), device=dev)
                 autotune.apply(B, tiles, tile_prec)
                 slots = [B.add(op, b, x, rtol=1e-8, mixed=(mode != "fp64")) for op, b, x in zip(mops, rhs, xs)]
                 out = B.run_all(iters_per_step=20)

@@ -175,27 +175,31 @@ int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);
 /* ------------------------------------------------------------------ batches
  * Many independent solves (different meshes, orders 1..11, FP64 or mixed
  * precision) advance together: each batched step runs one CG iteration of
- * every active solve in seven launches (persistent kernels over work lists of
- * (solve, element tile) and (solve, vector tile) items, plus one work-group
- * per solve for the scalars).  Every solve's arithmetic and reduction order
- * are those of sem_cg, so an FP64 solve gives the same bits in a batch as
- * alone.  Solves join and leave between steps (continuous batching); the
- * step's captured graph does not change when they do.  The batch holds no
- * memory of its own on the device beyond its workspace; each solve keeps its
- * state in its sem_ctx workspace.  Calls on one batch must not overlap. */
+ * every active solve.  A one-work-group schedule kernel first builds, on the
+ * device, compact work lists of the solves that have operator work in each
+ * (arithmetic class, order) bin and of the streaming tiles of every
+ * unfinished solve; then one persistent operator launch per bin in use (each
+ * compiled for its order), two streaming launches and one work-group per
+ * solve for the scalars.  Every solve's arithmetic and reduction order are
+ * those of sem_cg, so an FP64 solve gives the same bits in a batch as alone.
+ * Solves join and leave between steps (continuous batching); the step's
+ * graph is captured again only when the set of bins in use or the tiles
+ * change.  The batch holds no memory of its own on the device beyond its
+ * workspace; each solve keeps its state in its sem_ctx workspace.  Calls on
+ * one batch must not overlap. */
 typedef struct sem_batch sem_batch;
 
-/* Workspace of a batch: slot table, work lists (capacities in items: one
- * operator item per tile of elements, one vector item per 2048 entries of a
- * solve's L-vector), status records.  0 for invalid capacities. */
-size_t sem_batch_workspace_bytes(int max_slots, int64_t max_op_items, int64_t max_vec_items);
+/* Workspace of a batch of up to max_slots solves (1..4096): slot table, the
+ * schedule's work lists (34 bins of max_slots entries), status records.  0
+ * for an invalid max_slots. */
+size_t sem_batch_workspace_bytes(int max_slots);
 
 /* Create a batch in `dev_ws` (256-byte aligned).  Synchronous. */
-int sem_batch_create(int max_slots, int64_t max_op_items, int64_t max_vec_items, void *dev_ws,
-                     size_t ws_bytes, void *stream, sem_batch **out);
+int sem_batch_create(int max_slots, void *dev_ws, size_t ws_bytes, void *stream, sem_batch **out);
 
-/* Elements per operator item for one order (autotuner hook; applies to solves
- * added afterwards).  SEM_ERR_UNSUPPORTED for a tile that is not compiled. */
+/* Elements per operator item for one order (autotuner hook; applies from the
+ * next step on, to every solve of that order: the bits do not depend on it).
+ * SEM_ERR_UNSUPPORTED for a tile that is not compiled. */
 int sem_batch_set_tile(sem_batch *batch, int order, int elements_per_item);
 
 /* Start the solve of A x = b on ctx (tolerance mode, opts as for sem_cg;

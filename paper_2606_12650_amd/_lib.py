@@ -77,8 +77,8 @@ def _declare(lib):
         "vec_dot": (ctypes.c_int, [i64, vp, vp, vp, vp, vp, sz, vp]),
         "sem_export": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),
         "sem_last_error": (ctypes.c_char_p, []),
-        "sem_batch_workspace_bytes": (sz, [ctypes.c_int, i64, i64]),
-        "sem_batch_create": (ctypes.c_int, [ctypes.c_int, i64, i64, vp, sz, vp, P(vp)]),
+        "sem_batch_workspace_bytes": (sz, [ctypes.c_int]),
+        "sem_batch_create": (ctypes.c_int, [ctypes.c_int, vp, sz, vp, P(vp)]),
         "sem_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "sem_batch_add": (ctypes.c_int, [vp, vp, vp, vp, P(SemCgOpts), P(ctypes.c_int), vp]),
         "sem_batch_step": (ctypes.c_int, [vp, ctypes.c_int, vp]),

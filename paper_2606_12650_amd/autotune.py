@@ -19,7 +19,7 @@ import time
 import torch
 
 from . import _lib as L
-from .batch import SemBatch, items_for
+from .batch import SemBatch
 from .sem import SemOperator
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sem_mi355x", "tiles.json")
@@ -44,7 +44,7 @@ def _key(ctx: dict, prec: str, order: int) -> str:
 
 
 def supported_tiles(order: int, device) -> list[int]:
-    B = SemBatch(1, 1, 1, device=device)
+    B = SemBatch(1, device=device)
     out = []
     for epb in CANDIDATES:
         if L.lib().sem_batch_set_tile(B._h, int(order), int(epb)) == L.SEM_OK:
@@ -61,9 +61,7 @@ def _time_tile(order: int, epb: int, prec: str, device, nel: int, instances: int
         b = torch.ones(op.L, dtype=torch.float64, device=device)
         ops.append(op)
         bs.append(b)
-    nop = sum(items_for(op, epb)[0] for op in ops)
-    nvec = sum(items_for(op, 1)[1] for op in ops)
-    B = SemBatch(instances, nop + 8, nvec + 8, device=device)
+    B = SemBatch(instances, device=device)
     B.set_tile(order, epb)
     for op, b in zip(ops, bs):
         # a tolerance no solve reaches in the timed steps: every step does full work

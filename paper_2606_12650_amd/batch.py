@@ -21,7 +21,7 @@ VEC_TILE = 2048  # entries per streaming item
 
 
 def items_for(op: SemOperator, epb: int) -> tuple[int, int]:
-    """(operator items, vector items) a solve on ``op`` occupies."""
+    """(operator items, vector items) a solve on ``op`` gives each iteration."""
     return math.ceil(op.E / epb), math.ceil(op.L / VEC_TILE)
 
 
@@ -31,20 +31,19 @@ def default_epb(order: int) -> int:
 
 
 class SemBatch:
-    def __init__(self, max_slots: int, max_op_items: int, max_vec_items: int, device="cuda"):
+    def __init__(self, max_slots: int, device="cuda"):
         self.device = torch.device(device)
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         lib = L.lib()
-        nbytes = int(lib.sem_batch_workspace_bytes(int(max_slots), int(max_op_items), int(max_vec_items)))
+        nbytes = int(lib.sem_batch_workspace_bytes(int(max_slots)))
         if nbytes == 0:
-            raise ValueError("invalid batch capacities")
+            raise ValueError("max_slots must be in 1..4096")
         self._ws_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         off = (-self._ws_raw.data_ptr()) % 256
         self.ws = self._ws_raw[off:off + nbytes]
         self._h = ctypes.c_void_p()
-        L.check("sem_batch_create", lib.sem_batch_create(int(max_slots), int(max_op_items),
-                                                          int(max_vec_items), _ptr(self.ws), nbytes,
+        L.check("sem_batch_create", lib.sem_batch_create(int(max_slots), _ptr(self.ws), nbytes,
                                                           _stream(self.device), ctypes.byref(self._h)))
         self.max_slots = int(max_slots)
         self._slots: dict[int, tuple] = {}

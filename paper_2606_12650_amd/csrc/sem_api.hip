@@ -581,29 +581,29 @@ int sem_export(sem_ctx *ctx, int field, double *dst, void *stream) {
 
 struct sem_batch {
   int max_slots;
-  int64_t max_op_items, max_vec_items;
   semk::BatchSlot *d_slots;
-  semk::BatchItem *d_op, *d_vec;
-  int *d_counts;
+  semk::BatchSched sched;
   semk::BatchStatus *d_status;
   std::vector<semk::BatchSlot> slots;  // host copies as uploaded at add/remove
   std::vector<sem_ctx *> ctx;          // null for a free slot
   std::vector<semk::BatchStatus> status;
-  std::vector<semk::BatchItem> op_host, vec_host;
-  int counts_host[4];
-  int epb[semk::kMaxOrder + 1];
+  semk::BatchTiles tiles;
   hipGraphExec_t graph;
+  // what the captured graph was built for: stream, iterations, the operator
+  // bins it launches and the tiles
   hipStream_t graph_stream;
   int graph_iters;
+  uint64_t graph_bins;
+  semk::BatchTiles graph_tiles;
 };
 
 namespace {
 
 struct BatchLayout {
-  size_t slots, op, vec, counts, status, total;
+  size_t slots, meta, slot, prefix, status, total;
 };
 
-BatchLayout batch_layout(int max_slots, int64_t max_op, int64_t max_vec) {
+BatchLayout batch_layout(int max_slots) {
   BatchLayout o;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -611,88 +611,72 @@ BatchLayout batch_layout(int max_slots, int64_t max_op, int64_t max_vec) {
     at = align_up(at + bytes);
     return off;
   };
+  const size_t bins = semk::kBatchBins + 1;
   o.slots = take((size_t)max_slots * sizeof(semk::BatchSlot));
-  o.op = take((size_t)max_op * sizeof(semk::BatchItem));
-  o.vec = take((size_t)max_vec * sizeof(semk::BatchItem));
-  o.counts = take(4 * sizeof(int));
+  o.meta = take(bins * 2 * sizeof(int));
+  o.slot = take(bins * (size_t)max_slots * sizeof(int));
+  o.prefix = take(bins * ((size_t)max_slots + 1) * sizeof(int));
   o.status = take((size_t)max_slots * sizeof(semk::BatchStatus));
   o.total = at;
   return o;
 }
 
-// Rebuild the work lists from the active slots: operator items grouped by
-// order (then slot), streaming items slot by slot.
-int batch_upload_items(sem_batch *B, hipStream_t s) {
-  B->op_host.clear();
-  B->vec_host.clear();
-  for (int order = 1; order <= semk::kMaxOrder; ++order)
-    for (int q = 0; q < B->max_slots; ++q) {
-      if (!B->ctx[q] || B->slots[q].N != order) continue;
-      const semk::BatchSlot &S = B->slots[q];
-      for (int64_t e0 = 0; e0 < S.E; e0 += S.epb) B->op_host.push_back({q, (int)e0});
-    }
+// Operator bins the occupied slots can use: an FP64 solve its order's FP64
+// bin, a mixed solve that and its low-precision bin.
+uint64_t batch_bins(const sem_batch *B) {
+  uint64_t m = 0;
   for (int q = 0; q < B->max_slots; ++q) {
     if (!B->ctx[q]) continue;
-    const int64_t nt = semk::vec_num_blocks(B->slots[q].L);
-    for (int64_t t = 0; t < nt; ++t) B->vec_host.push_back({q, (int)t});
+    const semk::BatchSlot &S = B->slots[q];
+    m |= 1ull << semk::batch_bin(0, S.N);
+    if (S.mixed) m |= 1ull << semk::batch_bin(S.mixed == SEM_F32 ? 1 : 2, S.N);
   }
-  if ((int64_t)B->op_host.size() > B->max_op_items || (int64_t)B->vec_host.size() > B->max_vec_items)
-    return fail(SEM_ERR_NOMEM, "sem_batch: work lists exceed the batch's item capacity");
-  B->counts_host[0] = (int)B->op_host.size();
-  B->counts_host[1] = (int)B->vec_host.size();
-  B->counts_host[2] = B->counts_host[3] = 0;
-  if (!B->op_host.empty())
-    SEM_HIP(hipMemcpyAsync(B->d_op, B->op_host.data(), B->op_host.size() * sizeof(semk::BatchItem),
-                           hipMemcpyHostToDevice, s));
-  if (!B->vec_host.empty())
-    SEM_HIP(hipMemcpyAsync(B->d_vec, B->vec_host.data(), B->vec_host.size() * sizeof(semk::BatchItem),
-                           hipMemcpyHostToDevice, s));
-  SEM_HIP(hipMemcpyAsync(B->d_counts, B->counts_host, sizeof(B->counts_host), hipMemcpyHostToDevice, s));
-  SEM_HIP(hipStreamSynchronize(s));
-  return SEM_OK;
+  return m;
 }
 
 }  // namespace
 
 extern "C" {
 
-size_t sem_batch_workspace_bytes(int max_slots, int64_t max_op_items, int64_t max_vec_items) {
-  if (max_slots < 1 || max_op_items < 1 || max_vec_items < 1) return 0;
-  return batch_layout(max_slots, max_op_items, max_vec_items).total;
+size_t sem_batch_workspace_bytes(int max_slots) {
+  if (max_slots < 1 || max_slots > semk::kBatchMaxSlots) return 0;
+  return batch_layout(max_slots).total;
 }
 
-int sem_batch_create(int max_slots, int64_t max_op_items, int64_t max_vec_items, void *dev_ws,
-                     size_t ws_bytes, void *stream, sem_batch **out) {
+int sem_batch_create(int max_slots, void *dev_ws, size_t ws_bytes, void *stream, sem_batch **out) {
   if (!out) return fail(SEM_ERR_ARG, "sem_batch_create: null output handle");
   *out = nullptr;
-  if (max_slots < 1 || max_slots > 65535 || max_op_items < 1 || max_vec_items < 1 ||
-      max_op_items > INT32_MAX || max_vec_items > INT32_MAX)
-    return fail(SEM_ERR_ARG, "sem_batch_create: capacities out of range");
+  if (max_slots < 1 || max_slots > semk::kBatchMaxSlots)
+    return fail(SEM_ERR_ARG, "sem_batch_create: max_slots out of range (1..4096)");
   if (!dev_ws || ((uintptr_t)dev_ws) % kAlign != 0)
     return fail(SEM_ERR_ARG, "sem_batch_create: workspace null or not 256-byte aligned");
-  const BatchLayout lay = batch_layout(max_slots, max_op_items, max_vec_items);
+  const BatchLayout lay = batch_layout(max_slots);
   if (ws_bytes < lay.total) return fail(SEM_ERR_NOMEM, "sem_batch_create: workspace too small");
+  hipError_t e = semk::batch_prepare();
+  if (e != hipSuccess) return hip_fail(e, "sem_batch_create: occupancy query");
   hipStream_t s = (hipStream_t)stream;
   sem_batch *B = new sem_batch();
   char *ws = (char *)dev_ws;
   B->max_slots = max_slots;
-  B->max_op_items = max_op_items;
-  B->max_vec_items = max_vec_items;
   B->d_slots = (semk::BatchSlot *)(ws + lay.slots);
-  B->d_op = (semk::BatchItem *)(ws + lay.op);
-  B->d_vec = (semk::BatchItem *)(ws + lay.vec);
-  B->d_counts = (int *)(ws + lay.counts);
+  B->sched.meta = (int *)(ws + lay.meta);
+  B->sched.slot = (int *)(ws + lay.slot);
+  B->sched.prefix = (int *)(ws + lay.prefix);
+  B->sched.max_slots = max_slots;
   B->d_status = (semk::BatchStatus *)(ws + lay.status);
   B->slots.assign(max_slots, semk::BatchSlot());
   for (auto &S : B->slots) std::memset(&S, 0, sizeof(S));
   B->ctx.assign(max_slots, nullptr);
   B->status.assign(max_slots, semk::BatchStatus());
-  for (int n = 0; n <= semk::kMaxOrder; ++n) B->epb[n] = (n >= 1 && n <= 11) ? semk::batch_default_epb(n) : 1;
+  std::memset(&B->tiles, 0, sizeof(B->tiles));
+  for (int n = 1; n <= semk::kBatchOrders; ++n) B->tiles.epb[n] = semk::batch_default_epb(n);
   B->graph = nullptr;
   B->graph_stream = nullptr;
   B->graph_iters = 0;
-  hipError_t e = hipMemcpyAsync(B->d_slots, B->slots.data(), max_slots * sizeof(semk::BatchSlot),
-                                hipMemcpyHostToDevice, s);
+  B->graph_bins = 0;
+  std::memset(&B->graph_tiles, 0, sizeof(B->graph_tiles));
+  e = hipMemcpyAsync(B->d_slots, B->slots.data(), max_slots * sizeof(semk::BatchSlot),
+                     hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
     std::vector<semk::BatchStatus> zero(max_slots);
     std::memset(zero.data(), 0, zero.size() * sizeof(semk::BatchStatus));
@@ -704,20 +688,16 @@ int sem_batch_create(int max_slots, int64_t max_op_items, int64_t max_vec_items,
     delete B;
     return hip_fail(e, "sem_batch_create: initialise slot table");
   }
-  int rc = batch_upload_items(B, s);
-  if (rc != SEM_OK) {
-    delete B;
-    return rc;
-  }
   *out = B;
   return SEM_OK;
 }
 
 int sem_batch_set_tile(sem_batch *B, int order, int elements_per_item) {
   if (!B) return fail(SEM_ERR_ARG, "sem_batch_set_tile: null handle");
-  if (order < semk::kMinOrder || order > 11 || !semk::batch_epb_supported(order, elements_per_item))
+  if (order < semk::kMinOrder || order > semk::kBatchOrders ||
+      !semk::batch_epb_supported(order, elements_per_item))
     return fail(SEM_ERR_UNSUPPORTED, "sem_batch_set_tile: tile not compiled for this order");
-  B->epb[order] = elements_per_item;
+  B->tiles.epb[order] = elements_per_item;
   return SEM_OK;
 }
 
@@ -756,7 +736,7 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   std::memset(&S, 0, sizeof(S));
   S.box = bx;
   S.N = bx.N;
-  S.epb = B->epb[bx.N];
+  S.vtiles = (int)semk::vec_num_blocks(bx.L());
   S.mixed = opts->mixed ? ctx->desc.lowprec : 0;
   S.active = 1;
   S.inner_total = 0;
@@ -797,18 +777,10 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   st0.bnorm2 = h.bnorm2;
   SEM_HIP(hipMemcpyAsync(B->d_slots + q, &S, sizeof(S), hipMemcpyHostToDevice, s));
   SEM_HIP(hipMemcpyAsync(B->d_status + q, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+  SEM_HIP(hipStreamSynchronize(s));
   B->slots[q] = S;
   B->ctx[q] = ctx;
   ctx->in_batch = 1;
-  int rc = batch_upload_items(B, s);
-  if (rc != SEM_OK) {
-    B->ctx[q] = nullptr;
-    ctx->in_batch = 0;
-    S.active = 0;
-    (void)hipMemcpyAsync(B->d_slots + q, &S, sizeof(S), hipMemcpyHostToDevice, s);
-    (void)batch_upload_items(B, s);
-    return rc;
-  }
   *slot_out = q;
   return SEM_OK;
 }
@@ -817,13 +789,17 @@ int sem_batch_step(sem_batch *B, int iters, void *stream) {
   if (!B) return fail(SEM_ERR_ARG, "sem_batch_step: null handle");
   if (iters < 1) return fail(SEM_ERR_ARG, "sem_batch_step: iters must be >= 1");
   hipStream_t s = (hipStream_t)stream;
-  if (s != nullptr && !(B->graph && B->graph_stream == s && B->graph_iters == iters)) {
+  const uint64_t bins = batch_bins(B);
+  const bool same = B->graph && B->graph_stream == s && B->graph_iters == iters &&
+                    B->graph_bins == bins &&
+                    std::memcmp(&B->graph_tiles, &B->tiles, sizeof(B->tiles)) == 0;
+  if (s != nullptr && !same) {
     if (B->graph) (void)hipGraphExecDestroy(B->graph);
     B->graph = nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess) {
       hipError_t e = hipSuccess;
       for (int it = 0; it < iters && e == hipSuccess; ++it)
-        e = semk::launch_batch_iteration(B->d_slots, B->max_slots, B->d_op, B->d_vec, B->d_counts,
+        e = semk::launch_batch_iteration(B->d_slots, B->max_slots, B->sched, B->tiles, bins,
                                          B->d_status, s);
       hipGraph_t g = nullptr;
       hipError_t e2 = hipStreamEndCapture(s, &g);
@@ -838,15 +814,18 @@ int sem_batch_step(sem_batch *B, int iters, void *stream) {
       B->graph = ex;
       B->graph_stream = s;
       B->graph_iters = iters;
+      B->graph_bins = bins;
+      B->graph_tiles = B->tiles;
     } else {
       (void)hipGetLastError();
     }
   }
-  if (B->graph && B->graph_stream == s && B->graph_iters == iters) {
+  if (s != nullptr && B->graph && B->graph_stream == s && B->graph_iters == iters &&
+      B->graph_bins == bins) {
     SEM_HIP(hipGraphLaunch(B->graph, s));
   } else {
     for (int it = 0; it < iters; ++it)
-      SEM_HIP(semk::launch_batch_iteration(B->d_slots, B->max_slots, B->d_op, B->d_vec, B->d_counts,
+      SEM_HIP(semk::launch_batch_iteration(B->d_slots, B->max_slots, B->sched, B->tiles, bins,
                                            B->d_status, s));
   }
   return SEM_OK;
@@ -890,10 +869,11 @@ int sem_batch_remove(sem_batch *B, int slot, void *stream) {
   semk::BatchSlot S;
   std::memset(&S, 0, sizeof(S));
   SEM_HIP(hipMemcpyAsync(B->d_slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, s));
+  SEM_HIP(hipStreamSynchronize(s));
   B->slots[slot] = S;
   B->ctx[slot]->in_batch = 0;
   B->ctx[slot] = nullptr;
-  return batch_upload_items(B, s);
+  return SEM_OK;
 }
 
 int sem_batch_destroy(sem_batch *B) {

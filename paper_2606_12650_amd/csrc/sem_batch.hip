@@ -1,15 +1,30 @@
 // Batched Jacobi-PCG: many independent solves of different sizes and orders
-// advance together, one CG iteration per batched step, in seven launches that
-// cover every solve.
+// advance together, one CG iteration per batched step.
 //
-// The two streaming launches and the two operator launches (FP64 and low-
-// precision work) are persistent kernels over work lists of (solve, tile) items; the three per-solve launches run one
-// work-group per solve.  Every item is computed by the same device functions
-// as a single solve (sem_ax_tile.h, sem_cg_dev.h) on the same tiles, and each
-// solve's reductions are summed in the same order, so an FP64 solve gives the
-// same bits alone and in a batch.  A mixed-precision solve moves through the
-// inner-outer phases (SlotPhase) on the device; the host only polls.
+// Every batched iteration starts with a one-work-group schedule kernel that
+// reads the solves' phases on the device and writes compact work lists: for
+// each (arithmetic class, order) bin the solves with operator work in it and
+// the prefix sums of their item counts, and the same for the streaming tiles
+// of every unfinished solve.  The operator work then runs in one persistent
+// launch per bin, each compiled for its order (work-group size, LDS and
+// registers of the single-solve kernel of that order), so a bin of small
+// elements is not held to the resources of the largest order.  Each work-group
+// takes a contiguous range of its bin's items and finds their solves by
+// searching the prefix sums; finished solves and idle phases take no items.
+// The per-solve scalars run one work-group per solve, the streaming launches
+// walk the streaming list in XCD-contiguous ranges.
+//
+// Every item is computed by the same device functions as a single solve
+// (sem_ax_tile.h, sem_cg_dev.h) and each solve's reductions are summed in
+// the same order (per-element and per-tile partials, fixed trees), so an FP64
+// solve gives the same bits alone and in a batch, for any tile size.  A
+// mixed-precision solve moves through the inner-outer phases (SlotPhase) on
+// the device; the host only polls.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
 
 #include "sem_ax_tile.h"
 #include "sem_cg_dev.h"
@@ -20,113 +35,181 @@ namespace semk {
 
 namespace {
 
-constexpr int kOpThreads = 256;
+constexpr int kSchedThreads = 1024;
 
-constexpr int align16(int v) { return (v + 15) / 16 * 16; }
-
-// LDS of the operator launches: the largest supported FP64 tile, and the
-// largest low-precision one (FP32 values).
-constexpr int kLdsBytes = 61 * 1024;
-constexpr int kLdsBytesLowp = 31 * 1024;
-
-// LDS needed by one operator tile (reduction buffer, D, two element tiles).
-template <int N1, int EPB, class P>
-constexpr int tile_lds_bytes() {
-  using TC = typename P::TC;
-  return align16(kOpThreads * 8) + align16(N1 * N1 * (int)sizeof(TC)) +
-         AxTile<N1>::kTiles * align16(EPB * AxTile<N1>::TILE * (int)sizeof(TC));
-}
-
-template <int N1, int EPB, class P, bool CG>
-__device__ __forceinline__ void op_tile(const BatchSlot &S, int e0, unsigned char *smem,
-                                        typename P::TV *u, typename P::TV *w,
-                                        const typename P::TV *r, const typename P::TV *minv,
-                                        typename P::TV *x, const typename P::TC *D,
-                                        const typename P::TG *G, double alpha, double beta) {
-  static_assert(tile_lds_bytes<N1, EPB, P>() <= (sizeof(typename P::TC) == 8 ? kLdsBytes : kLdsBytesLowp),
-                "operator tile exceeds the LDS budget");
-  static_assert(N1 * N1 * EPB <= kOpThreads, "operator tile exceeds the work-group");
-  using TC = typename P::TC;
-  double *sred = (double *)smem;
-  TC *sD = (TC *)(smem + align16(kOpThreads * 8));
-  TC *s1 = (TC *)((unsigned char *)sD + align16(N1 * N1 * (int)sizeof(TC)));
-  TC *s2 = (TC *)((unsigned char *)s1 + align16(EPB * AxTile<N1>::TILE * (int)sizeof(TC)));
-  TC *s3 = (TC *)((unsigned char *)s2 + align16(EPB * AxTile<N1>::TILE * (int)sizeof(TC)));
-  ax_tile<N1, EPB, P, CG>(S.E, e0, D, G, u, w, r, minv, x, alpha, beta, S.part_el, sD, s1, s2, s3,
-                          sred);
-}
-
-// FP64 work of an operator item: a CG iteration of an FP64 solve, or the
-// true-residual operator of a mixed solve's outer step.
-template <int N1, int EPB>
-__device__ __forceinline__ void op_item_f64(const BatchSlot &S, int e0, unsigned char *smem) {
-  if (S.mixed == 0) {
-    if (S.phase != kPhaseFp64 || S.st->done != kRunning) return;
-    op_tile<N1, EPB, PrecF64, true>(S, e0, smem, S.p, S.w, S.r, S.minv, S.x, S.D, S.G,
-                                    S.st->alpha, S.st->beta);
-  } else if (S.phase == kPhaseOuterOp) {
-    op_tile<N1, EPB, PrecF64, false>(S, e0, smem, S.x, S.w, nullptr, nullptr, nullptr, S.D, S.G,
-                                     0.0, 0.0);
-  }
-}
-
-// Low-precision work of an operator item: an inner iteration of a mixed solve.
-template <int N1, int EPB>
-__device__ __forceinline__ void op_item_lowp(const BatchSlot &S, int e0, unsigned char *smem) {
-  if (S.mixed == 0 || S.phase != kPhaseInner || S.st_in->done != kRunning) return;
-  if (S.mixed == SEM_F32)
-    op_tile<N1, EPB, PrecF32, true>(S, e0, smem, S.pin, S.win, S.rin, S.minv32, S.e, S.Dlo,
-                                    (const float *)S.Glo, S.st_in->alpha, S.st_in->beta);
-  else
-    op_tile<N1, EPB, PrecBF16, true>(S, e0, smem, S.pin, S.win, S.rin, S.minv32, S.e, S.Dlo,
-                                     (const uint16_t *)S.Glo, S.st_in->alpha, S.st_in->beta);
-}
-
-// Supported (order, elements per item) pairs, orders 1..11: the single-solve
-// kernel's tile and a larger one that fits 256 threads and the LDS budget.
+// Operator tiles compiled for batches (order, elements per work-group): the
+// single-solve kernel's tile and twice that where the FP64 LDS stays within
+// 64 KiB.
 #define SEM_BATCH_TILES(X)                                                    \
   X(1, 32) X(1, 64) X(2, 14) X(2, 28) X(3, 8) X(3, 16) X(4, 5) X(4, 10)      \
-  X(5, 3) X(5, 7) X(6, 2) X(6, 5) X(7, 2) X(7, 4) X(8, 1) X(8, 2) X(9, 1)   \
+  X(5, 3) X(5, 6) X(6, 2) X(6, 4) X(7, 2) X(7, 4) X(8, 1) X(8, 2) X(9, 1)   \
   X(9, 2) X(10, 1) X(11, 1)
 
-// Two persistent operator launches per batched iteration, one per
-// arithmetic class, so that the FP64 variants' register count does not
-// lower the occupancy of the low-precision inner iterations.
-template <bool F64>
-__global__ void __launch_bounds__(kOpThreads)
-    batch_op_kernel(const BatchSlot *__restrict__ slots, const BatchItem *__restrict__ items,
-                    const int *__restrict__ counts) {
-  __shared__ __align__(16) unsigned char smem[F64 ? kLdsBytes : kLdsBytesLowp];
-  const int n = counts[0];
-  for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const BatchItem item = items[it];
-    const BatchSlot &S = slots[item.slot];
-    if (!S.active) continue;
-    if (F64 ? (S.mixed != 0 && S.phase != kPhaseOuterOp) : (S.mixed == 0 || S.phase != kPhaseInner))
-      continue;
-#define OPCASE(n_, epb_)                                  \
-    if (S.N == n_ && S.epb == epb_) {                     \
-      if (F64)                                            \
-        op_item_f64<n_ + 1, epb_>(S, item.first, smem);   \
-      else                                                \
-        op_item_lowp<n_ + 1, epb_>(S, item.first, smem);  \
-      continue;                                           \
+template <int CLS>
+struct ClassPrec;
+template <>
+struct ClassPrec<0> {
+  using P = PrecF64;
+};
+template <>
+struct ClassPrec<1> {
+  using P = PrecF32;
+};
+template <>
+struct ClassPrec<2> {
+  using P = PrecBF16;
+};
+
+template <int N1, int EPB>
+struct OpCfg {
+  static constexpr int THREADS = (N1 * N1 * EPB + 63) / 64 * 64;
+};
+
+// Largest k in [0, cnt) with pre[k] <= w, for 1 <= cnt <= 4096 and
+// pre[0] = 0 <= w, pre strictly increasing.  Called by whole waves (all 64
+// lanes, uniform arguments); two rounds of one load per lane.
+__device__ inline int find_slot(const int *__restrict__ pre, int cnt, int w) {
+  const int lane = threadIdx.x & 63;
+  int base = 0, span = cnt;
+  if (cnt > 64) {
+    const int step = (cnt + 63) / 64;
+    const int idx = lane * step;
+    const unsigned long long m = __ballot(idx < cnt && pre[idx] <= w);
+    base = (63 - __clzll((long long)m)) * step;
+    span = min(step, cnt - base);
+  }
+  const unsigned long long m = __ballot(lane < span && pre[base + lane] <= w);
+  return base + 63 - __clzll((long long)m);
+}
+
+// [w0, w1): this work-group's contiguous share of n items.
+__device__ inline void block_range(int n, int *w0, int *w1) {
+  const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+  *w0 = (int)blockIdx.x * per;
+  *w1 = min(n, *w0 + per);
+}
+
+// Streaming items: each XCD takes one contiguous eighth of the list (the
+// neighbour copies that the gather-scatter reads then sit in its L2), and each
+// work-group a contiguous range of its XCD's eighth.  gridDim is a multiple
+// of kNumXcd.
+__device__ inline void xcd_block_range(int n, int *w0, int *w1) {
+  const int blocks = (int)gridDim.x / kNumXcd;
+  const int xcd = (int)blockIdx.x % kNumXcd, j = (int)blockIdx.x / kNumXcd;
+  const int xper = (n + kNumXcd - 1) / kNumXcd;
+  const int xs = xcd * xper, xe = min(n, xs + xper);
+  const int per = (max(0, xe - xs) + blocks - 1) / blocks;
+  *w0 = xs + j * per;
+  *w1 = min(xe, *w0 + per);
+}
+
+// ------------------------------------------------------------- schedule
+
+// Operator bin of a slot in this iteration (-1: no operator work).
+__device__ inline int slot_bin(const BatchSlot &S) {
+  if (!S.active || S.phase == kPhaseFinished) return -1;
+  int cls = -1;
+  if (S.mixed == 0) {
+    if (S.phase == kPhaseFp64 && S.st->done == kRunning) cls = 0;
+  } else if (S.phase == kPhaseOuterOp) {
+    cls = 0;
+  } else if (S.phase == kPhaseInner && S.st_in->done == kRunning) {
+    cls = S.mixed == SEM_F32 ? 1 : 2;
+  }
+  return cls < 0 ? -1 : batch_bin(cls, S.N);
+}
+
+__global__ void __launch_bounds__(kSchedThreads)
+    batch_schedule_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, BatchTiles tiles) {
+  __shared__ int s_bin[kBatchMaxSlots];
+  __shared__ int s_cnt[kBatchMaxSlots];
+  __shared__ int s_vt[kBatchMaxSlots];
+  const int ms = sc.max_slots;
+  for (int q = threadIdx.x; q < ms; q += blockDim.x) {
+    const BatchSlot &S = slots[q];
+    const int b = slot_bin(S);
+    s_bin[q] = b;
+    s_cnt[q] = b < 0 ? 0 : (int)((S.E + tiles.epb[S.N] - 1) / tiles.epb[S.N]);
+    s_vt[q] = (S.active && S.phase != kPhaseFinished) ? S.vtiles : 0;
+  }
+  __syncthreads();
+  // one wave per bin: ordered compaction by ballot, prefix sums by a wave scan
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int b = wave; b <= kBatchBins; b += kSchedThreads / 64) {
+    int off = 0, run = 0;
+    for (int c = 0; c < ms; c += 64) {
+      const int q = c + lane;
+      int n = 0;
+      if (q < ms) n = b == kBatchBins ? s_vt[q] : (s_bin[q] == b ? s_cnt[q] : 0);
+      const bool in = n > 0;
+      const unsigned long long m = __ballot(in);
+      const int pos = __popcll(m & ((1ull << lane) - 1ull));
+      int x = n;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+      }
+      if (in) {
+        sc.slot[b * ms + off + pos] = q;
+        sc.prefix[b * (ms + 1) + off + pos] = run + x - n;
+      }
+      off += __popcll(m);
+      run += __shfl(x, 63);
     }
-    SEM_BATCH_TILES(OPCASE)
-#undef OPCASE
+    if (lane == 0) {
+      sc.prefix[b * (ms + 1) + off] = run;
+      sc.meta[2 * b] = off;
+      sc.meta[2 * b + 1] = run;
+    }
   }
 }
 
-// Streaming items are walked so that each XCD takes one contiguous range of
-// the list (tiles of one solve are contiguous in it).
-__device__ inline void xcd_range(int n, int *start, int *end, int *step) {
-  const int per_xcd_blocks = gridDim.x / kNumXcd;
-  const int xcd = blockIdx.x % kNumXcd;
-  const int chunk = (n + kNumXcd - 1) / kNumXcd;
-  *start = xcd * chunk + blockIdx.x / kNumXcd;
-  *end = min(n, (xcd + 1) * chunk);
-  *step = per_xcd_blocks;
+// ------------------------------------------------------------- operator
+
+template <int N1, int EPB, int CLS>
+__global__ void __launch_bounds__((OpCfg<N1, EPB>::THREADS))
+    batch_op_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int bin) {
+  using P = typename ClassPrec<CLS>::P;
+  using TC = typename P::TC;
+  using T = AxTile<N1>;
+  __shared__ TC sD[N1 * N1];
+  __shared__ TC s1[EPB * T::TILE];
+  __shared__ TC s2[EPB * T::TILE];
+  __shared__ TC s3[T::kTiles == 3 ? EPB * T::TILE : 1];
+  __shared__ double sred[OpCfg<N1, EPB>::THREADS];
+  const int cnt = sc.meta[2 * bin], total = sc.meta[2 * bin + 1];
+  int w0, w1;
+  block_range(total, &w0, &w1);
+  if (w0 >= w1) return;
+  const int *pre = sc.prefix + bin * (sc.max_slots + 1);
+  const int *sl = sc.slot + bin * sc.max_slots;
+  int k = find_slot(pre, cnt, w0);
+  int first = pre[k], next = pre[k + 1];
+  for (int w = w0; w < w1; ++w) {
+    while (w >= next) {
+      ++k;
+      first = next;
+      next = pre[k + 1];
+    }
+    const BatchSlot &S = slots[sl[k]];
+    const int64_t e0 = (int64_t)(w - first) * EPB;
+    if constexpr (CLS == 0) {
+      if (S.mixed == 0)
+        ax_tile<N1, EPB, PrecF64, true>(S.E, e0, S.D, S.G, S.p, S.w, S.r, S.minv, S.x, S.st->alpha,
+                                        S.st->beta, S.part_el, sD, s1, s2, s3, sred);
+      else  // true-residual operator of a mixed solve's outer step
+        ax_tile<N1, EPB, PrecF64, false>(S.E, e0, S.D, S.G, S.x, S.w, nullptr, nullptr, nullptr,
+                                         0.0, 0.0, S.part_el, sD, s1, s2, s3, sred);
+    } else {
+      ax_tile<N1, EPB, P, true>(S.E, e0, S.Dlo, (const typename P::TG *)S.Glo, S.pin, S.win, S.rin,
+                                S.minv32, S.e, S.st_in->alpha, S.st_in->beta, S.part_el, sD, s1,
+                                s2, s3, sred);
+    }
+  }
 }
+
+// ------------------------------------------------------------- streaming
 
 template <int N1>
 __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double *sred) {
@@ -152,33 +235,10 @@ __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double
   }
 }
 
-__global__ void __launch_bounds__(kVecThreads)
-    batch_update_kernel(const BatchSlot *__restrict__ slots, const BatchItem *__restrict__ items,
-                        const int *__restrict__ counts) {
-  __shared__ double sred[kVecThreads / 64];
-  int start, end, step;
-  xcd_range(counts[1], &start, &end, &step);
-  for (int it = start; it < end; it += step) {
-    const BatchItem item = items[it];
-    const BatchSlot &S = slots[item.slot];
-    if (!S.active) continue;
-    switch (S.N) {
-#define UCASE(n_) \
-  case n_:        \
-    update_item<n_ + 1>(S, item.first, sred); \
-    break;
-      UCASE(1) UCASE(2) UCASE(3) UCASE(4) UCASE(5) UCASE(6)
-      UCASE(7) UCASE(8) UCASE(9) UCASE(10) UCASE(11)
-#undef UCASE
-      default:
-        break;
-    }
-  }
-}
-
-// Second streaming launch: the end of an FP64 solve (x += alpha p), the
-// correction of a mixed solve (e += alpha p, x += ||r|| e) and the inner
-// restart (r_in = r / ||r||, e = p = 0 and the partials of its scalars).
+// The end of an FP64 solve (x += alpha p), the correction of a mixed solve
+// (e += alpha p, x += ||r|| e) and the inner restart (r_in = r / ||r||,
+// e = p = 0 and the partials of its scalars); these phases are set by the
+// beta launch of the same iteration.
 template <int N1>
 __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double *sred) {
   if (S.phase == kPhaseFp64Done) {
@@ -204,29 +264,44 @@ __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double
   }
 }
 
+template <bool UPDATE>
 __global__ void __launch_bounds__(kVecThreads)
-    batch_finish_kernel(const BatchSlot *__restrict__ slots, const BatchItem *__restrict__ items,
-                        const int *__restrict__ counts) {
+    batch_vec_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
   __shared__ double sred[kVecThreads / 64];
-  int start, end, step;
-  xcd_range(counts[1], &start, &end, &step);
-  for (int it = start; it < end; it += step) {
-    const BatchItem item = items[it];
-    const BatchSlot &S = slots[item.slot];
-    if (!S.active) continue;
+  const int cnt = sc.meta[2 * kBatchBins], total = sc.meta[2 * kBatchBins + 1];
+  int w0, w1;
+  xcd_block_range(total, &w0, &w1);
+  if (w0 >= w1) return;
+  const int *pre = sc.prefix + kBatchBins * (sc.max_slots + 1);
+  const int *sl = sc.slot + kBatchBins * sc.max_slots;
+  int k = find_slot(pre, cnt, w0);
+  int first = pre[k], next = pre[k + 1];
+  for (int w = w0; w < w1; ++w) {
+    while (w >= next) {
+      ++k;
+      first = next;
+      next = pre[k + 1];
+    }
+    const BatchSlot &S = slots[sl[k]];
+    const int tile = w - first;
     switch (S.N) {
-#define FCASE(n_) \
-  case n_:        \
-    finish_item<n_ + 1>(S, item.first, sred); \
+#define VCASE(n_)                                \
+  case n_:                                       \
+    if (UPDATE)                                  \
+      update_item<n_ + 1>(S, tile, sred);        \
+    else                                         \
+      finish_item<n_ + 1>(S, tile, sred);        \
     break;
-      FCASE(1) FCASE(2) FCASE(3) FCASE(4) FCASE(5) FCASE(6)
-      FCASE(7) FCASE(8) FCASE(9) FCASE(10) FCASE(11)
-#undef FCASE
+      VCASE(1) VCASE(2) VCASE(3) VCASE(4) VCASE(5) VCASE(6)
+      VCASE(7) VCASE(8) VCASE(9) VCASE(10) VCASE(11)
+#undef VCASE
       default:
         break;
     }
   }
 }
+
+// ------------------------------------------------------------- scalars
 
 // Per-solve launches: one work-group of kFinThreads per slot.
 __global__ void __launch_bounds__(kFinThreads)
@@ -291,6 +366,51 @@ __global__ void __launch_bounds__(kFinThreads)
   }
 }
 
+// ------------------------------------------------------------- launch sizes
+
+// Resident work-groups of each persistent kernel on a device: the occupancy
+// the compiler's resource use allows, times the compute units.
+struct BatchGrids {
+  int op[kBatchClasses][kBatchOrders + 1][2];  // [class][order][tile: base, doubled]
+  int vec[2];                                  // update, finish
+};
+std::mutex g_grid_mu;
+std::map<int, BatchGrids> g_grids;
+
+template <class K>
+int resident_blocks(K kernel, int threads, int cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel),
+                                                   threads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * cus;
+}
+
+int tile_index(int N, int epb) { return epb == batch_default_epb(N) ? 0 : 1; }
+
+const BatchGrids *current_grids() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_grid_mu);
+  auto it = g_grids.find(dev);
+  return it == g_grids.end() ? nullptr : &it->second;
+}
+
+template <int N1, int EPB>
+hipError_t launch_op(int cls, const BatchGrids &g, const BatchSlot *slots, const BatchSched &sc,
+                     int bin, hipStream_t s) {
+  const int grid = g.op[cls][N1 - 1][tile_index(N1 - 1, EPB)];
+  const dim3 threads(OpCfg<N1, EPB>::THREADS);
+  if (cls == 0)
+    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 0>), dim3(grid), threads, 0, s, slots, sc, bin);
+  else if (cls == 1)
+    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 1>), dim3(grid), threads, 0, s, slots, sc, bin);
+  else
+    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 2>), dim3(grid), threads, 0, s, slots, sc, bin);
+  return hipSuccess;
+}
+
 }  // namespace
 
 int batch_default_epb(int N) {
@@ -306,19 +426,63 @@ bool batch_epb_supported(int N, int epb) {
   return false;
 }
 
-hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchItem *op_items,
-                                  const BatchItem *vec_items, const int *counts,
-                                  BatchStatus *status, hipStream_t s) {
-  hipLaunchKernelGGL(batch_op_kernel<true>, dim3(kBatchOpBlocks), dim3(kOpThreads), 0, s, slots,
-                     op_items, counts);
-  hipLaunchKernelGGL(batch_op_kernel<false>, dim3(kBatchOpBlocks), dim3(kOpThreads), 0, s, slots,
-                     op_items, counts);
+hipError_t batch_prepare() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lock(g_grid_mu);
+    if (g_grids.count(dev)) return hipSuccess;
+  }
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  BatchGrids g;
+  std::memset(&g, 0, sizeof(g));
+#define GCASE(n_, epb_)                                                                        \
+  g.op[0][n_][tile_index(n_, epb_)] =                                                          \
+      resident_blocks(batch_op_kernel<n_ + 1, epb_, 0>, OpCfg<n_ + 1, epb_>::THREADS, cus);    \
+  g.op[1][n_][tile_index(n_, epb_)] =                                                          \
+      resident_blocks(batch_op_kernel<n_ + 1, epb_, 1>, OpCfg<n_ + 1, epb_>::THREADS, cus);    \
+  g.op[2][n_][tile_index(n_, epb_)] =                                                          \
+      resident_blocks(batch_op_kernel<n_ + 1, epb_, 2>, OpCfg<n_ + 1, epb_>::THREADS, cus);
+  SEM_BATCH_TILES(GCASE)
+#undef GCASE
+  g.vec[0] = xcd_grid(resident_blocks(batch_vec_kernel<true>, kVecThreads, cus));
+  g.vec[1] = xcd_grid(resident_blocks(batch_vec_kernel<false>, kVecThreads, cus));
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> lock(g_grid_mu);
+  g_grids[dev] = g;
+  return hipSuccess;
+}
+
+hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSched &sched,
+                                  const BatchTiles &tiles, uint64_t bins, BatchStatus *status,
+                                  hipStream_t s) {
+  const BatchGrids *g = current_grids();
+  if (!g) return hipErrorNotInitialized;
+  hipLaunchKernelGGL(batch_schedule_kernel, dim3(1), dim3(kSchedThreads), 0, s, slots, sched, tiles);
+  for (int cls = 0; cls < kBatchClasses; ++cls)
+    for (int N = 1; N <= kBatchOrders; ++N) {
+      const int bin = batch_bin(cls, N);
+      if (!((bins >> bin) & 1u)) continue;
+      const int epb = tiles.epb[N];
+      bool launched = false;
+#define LCASE(n_, epb_)                                                 \
+  if (!launched && N == n_ && epb == epb_) {                            \
+    (void)launch_op<n_ + 1, epb_>(cls, *g, slots, sched, bin, s);       \
+    launched = true;                                                    \
+  }
+      SEM_BATCH_TILES(LCASE)
+#undef LCASE
+      if (!launched) return hipErrorInvalidValue;
+    }
   hipLaunchKernelGGL(batch_alpha_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
-  hipLaunchKernelGGL(batch_update_kernel, dim3(kBatchVecBlocks), dim3(kVecThreads), 0, s, slots,
-                     vec_items, counts);
+  hipLaunchKernelGGL((batch_vec_kernel<true>), dim3(g->vec[0]), dim3(kVecThreads), 0, s, slots,
+                     sched);
   hipLaunchKernelGGL(batch_beta_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
-  hipLaunchKernelGGL(batch_finish_kernel, dim3(kBatchVecBlocks), dim3(kVecThreads), 0, s, slots,
-                     vec_items, counts);
+  hipLaunchKernelGGL((batch_vec_kernel<false>), dim3(g->vec[1]), dim3(kVecThreads), 0, s, slots,
+                     sched);
   hipLaunchKernelGGL(batch_phase_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots, status);
   return hipGetLastError();
 }

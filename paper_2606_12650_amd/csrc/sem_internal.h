@@ -102,8 +102,8 @@ enum SlotPhase : int {
 struct BatchSlot {
   Box box;
   int N;
-  int epb;    // elements per operator item
-  int mixed;  // 0: FP64, else the low-precision copy's sem_prec
+  int vtiles;  // streaming tiles (vec_num_blocks(L))
+  int mixed;   // 0: FP64, else the low-precision copy's sem_prec
   int active;
   int phase;  // SlotPhase, written by the device
   int inner_total;
@@ -120,11 +120,6 @@ struct BatchSlot {
   double *part_el, *part_rr, *part_rz;
 };
 
-struct BatchItem {
-  int slot;
-  int first;  // first element (operator items) or tile index (streaming items)
-};
-
 // Compact per-slot status the host polls (written by the device).
 struct BatchStatus {
   int phase;
@@ -134,19 +129,47 @@ struct BatchStatus {
   double rnorm2, bnorm2;
 };
 
-// Persistent launch sizes of the batched kernels.
-constexpr int kBatchOpBlocks = 2048;
-constexpr int kBatchVecBlocks = 2048;
+// Operator work of a batched iteration is binned by arithmetic class and
+// order: class 0 is FP64 (CG iterations of FP64 solves, true-residual
+// operators of mixed solves), classes 1 and 2 the FP32 and BF16 inner
+// iterations.  Bin kBatchBins holds the streaming tiles of every unfinished
+// solve.
+constexpr int kBatchOrders = 11;  // batches take orders 1..11
+constexpr int kBatchClasses = 3;
+constexpr int kBatchBins = kBatchClasses * kBatchOrders;
+constexpr int kBatchMaxSlots = 4096;
+__host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }
 
-// Candidate operator tiles (elements per 256-thread work-group) per order;
-// batches take orders 1..11.
+// Work lists that the schedule kernel rebuilds on the device at the start of
+// every batched iteration (bins 0..kBatchBins, max_slots entries each): the
+// slots with work in the bin in ascending order, the exclusive prefix sums of
+// their item counts (one more entry: the total), and [count, total].
+struct BatchSched {
+  int *meta;
+  int *slot;
+  int *prefix;
+  int max_slots;
+};
+
+// Elements per operator item, by order (index 1..11).
+struct BatchTiles {
+  int epb[kBatchOrders + 1];
+};
+
+// Operator tiles compiled for batches: the single-solve kernel's elements per
+// work-group for each order, and twice that where it fits.
 int batch_default_epb(int N);
 bool batch_epb_supported(int N, int epb);
+// Resident work-groups of every batched kernel on the current device
+// (queried once per process; call before graph capture).
+hipError_t batch_prepare();
 
-// One batched iteration (seven launches) over every active slot.
-hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchItem *op_items,
-                                  const BatchItem *vec_items, const int *counts,
-                                  BatchStatus *status, hipStream_t s);
+// One batched iteration over every active slot: the schedule, one operator
+// launch per bin set in `bins` (bit cls * 11 + N - 1), the per-solve scalar
+// launches and the two streaming launches.
+hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSched &sched,
+                                  const BatchTiles &tiles, uint64_t bins, BatchStatus *status,
+                                  hipStream_t s);
 
 // ---------------------------------------------------------------- launchers
 // All return the hipError_t of the launch (hipGetLastError after it).

@@ -159,7 +159,7 @@ class GpuExecutor:
     the GPU from its seed."""
 
     def __init__(self, device="cuda", max_slots=64, mixed: str | None = "f32", iters_per_step=10,
-                 max_op_items=1 << 20, max_vec_items=1 << 18, tiles: dict | None = None,
+                 tiles: dict | None = None,
                  rtol=1e-8, keep_solutions=False):
         import torch
 
@@ -170,7 +170,7 @@ class GpuExecutor:
         self.mixed = mixed
         self.iters = int(iters_per_step)
         self.rtol = rtol
-        self.batch = SemBatch(max_slots, max_op_items, max_vec_items, device=self.device)
+        self.batch = SemBatch(max_slots, device=self.device)
         for order, epb in (tiles or {}).items():
             self.batch.set_tile(int(order), int(epb))
         self.slots: dict = {}

@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 if torch.cuda.is_available():
     import paper_2606_12650_amd as sem
     from paper_2606_12650_amd import _lib as L
-    from paper_2606_12650_amd.batch import SemBatch, default_epb, items_for
+    from paper_2606_12650_amd.batch import SemBatch
 
 DEV = "cuda:0"
 
@@ -53,9 +53,7 @@ def test_fp64_batched_equals_alone_all_orders():
     for A, b in insts:
         x, res = A.cg(b, rtol=1e-8)
         alone.append((x.clone(), res))
-    nop = sum(items_for(A, default_epb(A.order))[0] for A, _ in insts)
-    nvec = sum(items_for(A, 1)[1] for A, _ in insts)
-    B = SemBatch(len(insts) + 2, nop + 16, nvec + 16, device=DEV)
+    B = SemBatch(len(insts) + 2, device=DEV)
     slots = [B.add(A, b) for A, b in insts]
     res = B.run_all(iters_per_step=7)
     for k, (s, (xa, ra)) in enumerate(zip(slots, alone)):
@@ -70,17 +68,40 @@ def test_fp64_batched_equals_alone_all_orders():
     assert torch.equal(x, alone[0][0])
 
 
-@pytest.mark.parametrize("order,tile", [(3, 16), (5, 7), (7, 4), (9, 2)])
+@pytest.mark.parametrize("order,tile", [(3, 16), (5, 6), (7, 4), (9, 2)])
 def test_tile_shape_does_not_change_bits(order, tile):
     A, b = _instance(7, 3, 2, 2, order)
     x0, r0 = A.cg(b, rtol=1e-8)
     x0 = x0.clone()
-    B = SemBatch(2, 64, 64, device=DEV)
+    B = SemBatch(2, device=DEV)
     B.set_tile(order, tile)
     s = B.add(A, b)
     res = B.run_all(iters_per_step=10)
     assert res[s].iters == r0.iters and torch.equal(B.solution(s), x0)
     B.remove(s)
+
+
+def test_many_slots_and_tile_change_between_steps():
+    """More solves than one wave of the schedule (the two-level slot search),
+    in every order bin, with a tile change between steps: each result has
+    the bits of its solve alone."""
+    insts = []
+    for i in range(150):
+        N = 1 + i % 11
+        insts.append(_instance(200 + i, 1 + i % 2, 1 + (i // 2) % 2, 1 + (i // 4) % 2, N))
+    alone = []
+    for A, b in insts:
+        x, r = A.cg(b, rtol=1e-8)
+        alone.append((x.clone(), r.iters))
+    B = SemBatch(160, device=DEV)
+    slots = [B.add(A, b) for A, b in insts]
+    B.step(4)
+    B.set_tile(3, 16)
+    B.set_tile(7, 4)
+    res = B.run_all(iters_per_step=6)
+    for s, (xa, ia) in zip(slots, alone):
+        assert res[s].status == 0 and res[s].iters == ia
+        assert torch.equal(B.solution(s), xa)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -91,7 +112,7 @@ def test_mixed_batched_matches_alone(prec):
     for A, b in insts:
         x, r = A.cg(b, rtol=1e-8, mixed=True)
         alone.append((x.clone(), r))
-    B = SemBatch(8, 512, 512, device=DEV)
+    B = SemBatch(8, device=DEV)
     slots = [B.add(A, b, mixed=True) for A, b in insts]
     res = B.run_all(iters_per_step=9)
     for s, (xa, ra), (A, b) in zip(slots, alone, insts):
@@ -116,7 +137,7 @@ def test_continuous_batching_join_leave_and_isolation():
         alone.append(x.clone())
     bad_A, bad_b = _instance(99, 2, 2, 2, 5)
     bad_b[int(torch.nonzero(bad_b)[0])] = float("nan")
-    B = SemBatch(8, 2048, 2048, device=DEV)
+    B = SemBatch(8, device=DEV)
     slot_of = {}
     for k in range(3):
         A, b, lp = insts[k]
@@ -151,7 +172,7 @@ def test_continuous_batching_join_leave_and_isolation():
 
 def test_batched_vs_oracle_small():
     cases = [((2, 2, 2), 3), ((2, 3, 2), 5)]
-    B = SemBatch(4, 64, 64, device=DEV)
+    B = SemBatch(4, device=DEV)
     data = []
     for i, ((nx, ny, nz), N) in enumerate(cases):
         pr = op.Problem(nx, ny, nz, N, 0.05)
@@ -171,7 +192,7 @@ def test_batched_vs_oracle_small():
 
 def test_batch_errors():
     A, b = _instance(1, 2, 2, 2, 12)
-    B = SemBatch(1, 16, 16, device=DEV)
+    B = SemBatch(1, device=DEV)
     with pytest.raises(sem.SemError):
         B.add(A, b)  # order 12 is not batched
     A2, b2 = _instance(2, 2, 2, 2, 3)

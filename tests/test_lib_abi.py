@@ -67,3 +67,16 @@ def test_argument_errors_return_codes_without_launching():
     assert lib.sem_nlocal(None) == -1
     assert lib.sem_destroy(None) == L.SEM_ERR_ARG
     assert lib.vec_dot_workspace_bytes(2049) == 16
+
+
+def test_batch_workspace_and_create_arguments_host_only():
+    lib = L.lib()
+    assert lib.sem_batch_workspace_bytes(0) == 0
+    assert lib.sem_batch_workspace_bytes(4097) == 0
+    one, many = lib.sem_batch_workspace_bytes(1), lib.sem_batch_workspace_bytes(256)
+    assert 0 < one < many
+    h = ctypes.c_void_p()
+    assert lib.sem_batch_create(0, None, 0, None, ctypes.byref(h)) == L.SEM_ERR_ARG
+    assert lib.sem_batch_create(4, None, many, None, ctypes.byref(h)) == L.SEM_ERR_ARG
+    assert not h.value
+

@@ -48,7 +48,7 @@ def lattice_to_lvector(grid: np.ndarray, nx: int, ny: int, nz: int, N: int) -> n
     n = N + 1
     win = np.lib.stride_tricks.sliding_window_view(grid, (n, n, n))[::N, ::N, ::N]
     assert win.shape == (nz, ny, nx, n, n, n)
-    return np.ascontiguousarray(win).reshape(nx * ny * nz, n, n, n)
+    return np.array(win, copy=True).reshape(nx * ny * nz, n, n, n)  # own, writable memory
 
 
 def random_lattice(seed: int, nx: int, ny: int, nz: int, N: int, zero_boundary: bool = True) -> np.ndarray:
