@@ -142,10 +142,9 @@ def bench_batching(args, dev) -> dict:
             if mode == "bf16":
                 mops = [sem.SemOperator(sp["nx"], sp["ny"], sp["nz"], sp["N"], sp["amp"], lowprec="bf16",
                                         device=dev) for sp in specs]
-            tile_prec = "f64" if mode == "fp64" else mode
             def run_batch():
                 B = SemBatch(len(mops), device=dev)
-                autotune.apply(B, tiles, tile_prec)
+                autotune.apply(B, tiles)
                 slots = [B.add(op, b, x, rtol=1e-8, mixed=(mode != "fp64")) for op, b, x in zip(mops, rhs, xs)]
                 out = B.run_all(iters_per_step=20)
                 for q in slots:

@@ -80,12 +80,20 @@ typedef struct {
   int32_t lowprec;          /* SEM_F64 (none), SEM_F32 or SEM_BF16: also keep a
                                rounded copy of G for the inner solver of the
                                mixed-precision CG                              */
-  int32_t flags;            /* 0, or SEM_FLAG_MFMA: the low-precision copy's D
-                               contractions run on the matrix cores (MFMA,
-                               FP32 accumulation) instead of the vector ALUs */
+  int32_t flags;            /* which element kernel the operators of this mesh
+                               run (FP64 and the low-precision copy):
+                               0: the faster one for the order and precision
+                                  as measured on MI355X (matrix cores from
+                                  N = 7 in FP64 and from N = 11 in FP32/BF16,
+                                  vector ALUs below);
+                               SEM_FLAG_MFMA: always the matrix-core kernel
+                                  (D contractions as f64 MFMA, or f32 / bf16
+                                  MFMA with FP32 accumulation);
+                               SEM_FLAG_VALU: always the vector-ALU kernel.
+                               Results agree up to rounding order. */
 } sem_mesh_desc;
 
-enum { SEM_FLAG_MFMA = 1 };
+enum { SEM_FLAG_MFMA = 1, SEM_FLAG_VALU = 2 };
 
 /* Device bytes sem_setup needs for this mesh (0 if the descriptor is invalid).
  * It covers G, the Jacobi diagonal, D, the CG vectors and reduction scratch;
@@ -197,10 +205,14 @@ size_t sem_batch_workspace_bytes(int max_slots);
 /* Create a batch in `dev_ws` (256-byte aligned).  Synchronous. */
 int sem_batch_create(int max_slots, void *dev_ws, size_t ws_bytes, void *stream, sem_batch **out);
 
-/* Elements per operator item for one order (autotuner hook; applies from the
- * next step on, to every solve of that order: the bits do not depend on it).
- * SEM_ERR_UNSUPPORTED for a tile that is not compiled. */
-int sem_batch_set_tile(sem_batch *batch, int order, int elements_per_item);
+/* Elements per operator item for one precision (SEM_F64 for FP64 solves and
+ * the outer steps of mixed ones, SEM_F32 / SEM_BF16 for inner iterations) and
+ * order (autotuner hook; applies from the next step on, to every solve of
+ * that order: the bits do not depend on it).  SEM_ERR_UNSUPPORTED for a tile
+ * that is not compiled.  A batch runs the default element kernel of each
+ * precision and order (see sem_mesh_desc.flags); sem_batch_add refuses a
+ * context set up with a forced kernel. */
+int sem_batch_set_tile(sem_batch *batch, int prec, int order, int elements_per_item);
 
 /* Start the solve of A x = b on ctx (tolerance mode, opts as for sem_cg;
  * opts->mixed needs ctx's low-precision copy) in a free slot.  b and x must

@@ -22,7 +22,7 @@ SEM_ERR_UNSUPPORTED = -6
 SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_AX_LOCAL, SEM_AX_ASSEMBLED, SEM_AX_MASKED = 0, 1, 3
 SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2, 3, 4
-SEM_FLAG_MFMA = 1
+SEM_FLAG_MFMA, SEM_FLAG_VALU = 1, 2
 
 # Every symbol include/sem.h declares.
 EXPORTS = (
@@ -79,7 +79,7 @@ def _declare(lib):
         "sem_last_error": (ctypes.c_char_p, []),
         "sem_batch_workspace_bytes": (sz, [ctypes.c_int]),
         "sem_batch_create": (ctypes.c_int, [ctypes.c_int, vp, sz, vp, P(vp)]),
-        "sem_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "sem_batch_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "sem_batch_add": (ctypes.c_int, [vp, vp, vp, vp, P(SemCgOpts), P(ctypes.c_int), vp]),
         "sem_batch_step": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "sem_batch_poll": (ctypes.c_int, [vp, P(ctypes.c_int), ctypes.c_int, P(ctypes.c_int),

@@ -43,11 +43,14 @@ def _key(ctx: dict, prec: str, order: int) -> str:
     return f"{ctx['device::name']}|{ctx['device::arch']}|{ctx['device::driver']}|{prec}|N{order}"
 
 
-def supported_tiles(order: int, device) -> list[int]:
+_PREC_CODE = {"f64": L.SEM_F64, "f32": L.SEM_F32, "bf16": L.SEM_BF16}
+
+
+def supported_tiles(order: int, device, prec: str = "f64") -> list[int]:
     B = SemBatch(1, device=device)
     out = []
     for epb in CANDIDATES:
-        if L.lib().sem_batch_set_tile(B._h, int(order), int(epb)) == L.SEM_OK:
+        if L.lib().sem_batch_set_tile(B._h, _PREC_CODE[prec], int(order), int(epb)) == L.SEM_OK:
             out.append(epb)
     B.close()
     return out
@@ -62,7 +65,7 @@ def _time_tile(order: int, epb: int, prec: str, device, nel: int, instances: int
         ops.append(op)
         bs.append(b)
     B = SemBatch(instances, device=device)
-    B.set_tile(order, epb)
+    B.set_tile(order, epb, "f64" if lowprec is None else lowprec)
     for op, b in zip(ops, bs):
         # a tolerance no solve reaches in the timed steps: every step does full work
         B.add(op, b, rtol=1e-30, mixed=lowprec is not None, max_iter=10 ** 6, inner_max=10 ** 6)
@@ -101,7 +104,7 @@ def tune(orders=(3, 5, 7, 9, 11), precisions=("f64", "f32", "bf16"), device="cud
                     continue
                 nel = elements or max(4, int(round((12000.0 / (order + 1) ** 3) ** (1 / 3) * 4)))
                 best, best_t = None, float("inf")
-                for epb in supported_tiles(order, dev):
+                for epb in supported_tiles(order, dev, prec):
                     t = _time_tile(order, epb, prec, dev, nel, instances, iters)
                     timings[(prec, order, epb)] = t
                     if t < best_t:
@@ -117,7 +120,9 @@ def tune(orders=(3, 5, 7, 9, 11), precisions=("f64", "f32", "bf16"), device="cud
     return out
 
 
-def apply(batch: SemBatch, tiles: dict, prec: str) -> None:
-    for order, epb in tiles.get(prec, {}).items():
-        if epb:
-            batch.set_tile(int(order), int(epb))
+def apply(batch: SemBatch, tiles: dict, precs=("f64", "f32", "bf16")) -> None:
+    """Set the tuned tiles of the given precisions on a batch."""
+    for prec in precs:
+        for order, epb in tiles.get(prec, {}).items():
+            if epb:
+                batch.set_tile(int(order), int(epb), prec)

@@ -18,6 +18,7 @@ from . import _lib as L
 from .sem import CgResult, SemOperator, _ptr, _stream
 
 VEC_TILE = 2048  # entries per streaming item
+_PREC_CODE = {"f64": L.SEM_F64, "f32": L.SEM_F32, "bf16": L.SEM_BF16}
 
 
 def items_for(op: SemOperator, epb: int) -> tuple[int, int]:
@@ -25,8 +26,13 @@ def items_for(op: SemOperator, epb: int) -> tuple[int, int]:
     return math.ceil(op.E / epb), math.ceil(op.L / VEC_TILE)
 
 
-def default_epb(order: int) -> int:
+def default_epb(order: int, prec: str = "f64") -> int:
+    """The library's default elements per operator item (the single-solve tile
+    of the element kernel that order and precision run by default)."""
     n1 = order + 1
+    if (order >= 7) if prec == "f64" else (order >= 11):  # matrix-core tile
+        nt = (n1 * n1 + 15) // 16
+        return 1 if nt >= 8 else 8 // nt
     return 1 if n1 * n1 >= 128 else 128 // (n1 * n1)
 
 
@@ -62,8 +68,11 @@ class SemBatch:
         except Exception:
             pass
 
-    def set_tile(self, order: int, elements_per_item: int) -> None:
-        L.check("sem_batch_set_tile", L.lib().sem_batch_set_tile(self._h, int(order), int(elements_per_item)))
+    def set_tile(self, order: int, elements_per_item: int, prec: str = "f64") -> None:
+        """Elements per operator item of one order for FP64 work ("f64") or the
+        inner iterations of mixed solves ("f32", "bf16")."""
+        L.check("sem_batch_set_tile", L.lib().sem_batch_set_tile(self._h, _PREC_CODE[prec], int(order),
+                                                                  int(elements_per_item)))
 
     def add(self, op: SemOperator, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8,
             mixed: bool = False, max_iter: int = 0, inner_rtol: float = 0.0, inner_max: int = 0) -> int:

@@ -57,9 +57,8 @@ bool desc_valid(const sem_mesh_desc *d, std::string *why) {
     *why = "lowprec must be SEM_F64, SEM_F32 or SEM_BF16";
     return false;
   }
-  if (d->flags != 0 && d->flags != SEM_FLAG_MFMA) { *why = "flags must be 0 or SEM_FLAG_MFMA"; return false; }
-  if (d->flags == SEM_FLAG_MFMA && d->lowprec == SEM_F64) {
-    *why = "SEM_FLAG_MFMA needs a low-precision copy (lowprec SEM_F32 or SEM_BF16)";
+  if (d->flags != 0 && d->flags != SEM_FLAG_MFMA && d->flags != SEM_FLAG_VALU) {
+    *why = "flags must be 0, SEM_FLAG_MFMA or SEM_FLAG_VALU";
     return false;
   }
   if (!std::isfinite(d->deform_amp)) { *why = "deform_amp must be finite"; return false; }
@@ -208,7 +207,7 @@ namespace {
 // one-group step for beta, the residual and the done flag.
 int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_f64(b, c->D, c->G, c->p, c->w, c->r, c->minv, x, c->st, c->part_ax, s));
+  SEM_HIP(semk::launch_ax_f64(b, c->desc.flags, c->D, c->G, c->p, c->w, c->r, c->minv, x, c->st, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
   SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_vec_blocks, s));
@@ -219,7 +218,7 @@ int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
 // on FP32 vectors with the rounded operator; the inner correction e plays x.
 int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->desc.flags & SEM_FLAG_MFMA, c->Dlo, c->Glo,
+  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->desc.flags, c->Dlo, c->Glo,
                                c->pin, c->win, c->rin, c->minv32, c->e, c->st_in, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
@@ -415,12 +414,12 @@ int sem_ax(sem_ctx *ctx, const double *u, double *w, int mode, void *stream) {
     return fail(SEM_ERR_ARG, "sem_ax: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
   if (mode == SEM_AX_LOCAL) {
-    SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
+    SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->desc.flags, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, s));
     return SEM_OK;
   }
   // element-local result into the workspace, then the gather-scatter pull
-  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->D, ctx->G, const_cast<double *>(u), ctx->w, nullptr,
+  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->desc.flags, ctx->D, ctx->G, const_cast<double *>(u), ctx->w, nullptr,
                               nullptr, nullptr, nullptr, nullptr, s));
   SEM_HIP(semk::launch_gather(ctx->box, ctx->w, w,
                               mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));
@@ -481,7 +480,7 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
       if (rc != SEM_OK) return rc;
       inner_total += hi.iter;
       SEM_HIP(semk::launch_outer_correct(bx, x, ctx->e, ctx->pin, ctx->st_in, ctx->st, s));
-      SEM_HIP(semk::launch_ax_f64(bx, ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
+      SEM_HIP(semk::launch_ax_f64(bx, ctx->desc.flags, ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
                                   nullptr, s));
       SEM_HIP(semk::launch_outer_step(bx, b, ctx->w, ctx->r, ctx->st, ctx->part_rr, s));
       SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -513,7 +512,7 @@ int sem_ax_lowp(sem_ctx *ctx, const float *u, float *w, int mode, void *stream) 
     return fail(SEM_ERR_ARG, "sem_ax_lowp: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
   float *dst = mode == SEM_AX_LOCAL ? w : ctx->win;
-  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->desc.flags & SEM_FLAG_MFMA, ctx->Dlo,
+  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->desc.flags, ctx->Dlo,
                                ctx->Glo, const_cast<float *>(u), dst, nullptr, nullptr, nullptr, nullptr,
                                nullptr, s));
   if (mode != SEM_AX_LOCAL)
@@ -622,14 +621,16 @@ BatchLayout batch_layout(int max_slots) {
 }
 
 // Operator bins the occupied slots can use: an FP64 solve its order's FP64
-// bin, a mixed solve that and its low-precision bin.
+// CG bin, a mixed solve its low-precision bin and its outer operator bin.
 uint64_t batch_bins(const sem_batch *B) {
   uint64_t m = 0;
   for (int q = 0; q < B->max_slots; ++q) {
     if (!B->ctx[q]) continue;
     const semk::BatchSlot &S = B->slots[q];
-    m |= 1ull << semk::batch_bin(0, S.N);
-    if (S.mixed) m |= 1ull << semk::batch_bin(S.mixed == SEM_F32 ? 1 : 2, S.N);
+    if (S.mixed)
+      m |= (1ull << semk::batch_bin(3, S.N)) | (1ull << semk::batch_bin(S.mixed == SEM_F32 ? 1 : 2, S.N));
+    else
+      m |= 1ull << semk::batch_bin(0, S.N);
   }
   return m;
 }
@@ -669,7 +670,8 @@ int sem_batch_create(int max_slots, void *dev_ws, size_t ws_bytes, void *stream,
   B->ctx.assign(max_slots, nullptr);
   B->status.assign(max_slots, semk::BatchStatus());
   std::memset(&B->tiles, 0, sizeof(B->tiles));
-  for (int n = 1; n <= semk::kBatchOrders; ++n) B->tiles.epb[n] = semk::batch_default_epb(n);
+  for (int c = 0; c < semk::kBatchClasses; ++c)
+    for (int n = 1; n <= semk::kBatchOrders; ++n) B->tiles.epb[c][n] = semk::batch_default_epb(c, n);
   B->graph = nullptr;
   B->graph_stream = nullptr;
   B->graph_iters = 0;
@@ -692,12 +694,15 @@ int sem_batch_create(int max_slots, void *dev_ws, size_t ws_bytes, void *stream,
   return SEM_OK;
 }
 
-int sem_batch_set_tile(sem_batch *B, int order, int elements_per_item) {
+int sem_batch_set_tile(sem_batch *B, int prec, int order, int elements_per_item) {
   if (!B) return fail(SEM_ERR_ARG, "sem_batch_set_tile: null handle");
+  const int cls = prec == SEM_F64 ? 0 : prec == SEM_F32 ? 1 : prec == SEM_BF16 ? 2 : -1;
+  if (cls < 0) return fail(SEM_ERR_ARG, "sem_batch_set_tile: prec must be SEM_F64, SEM_F32 or SEM_BF16");
   if (order < semk::kMinOrder || order > semk::kBatchOrders ||
-      !semk::batch_epb_supported(order, elements_per_item))
+      !semk::batch_epb_supported(cls, order, elements_per_item))
     return fail(SEM_ERR_UNSUPPORTED, "sem_batch_set_tile: tile not compiled for this order");
-  B->tiles.epb[order] = elements_per_item;
+  B->tiles.epb[cls][order] = elements_per_item;
+  if (cls == 0) B->tiles.epb[3][order] = elements_per_item;  // the outer steps' FP64 operator
   return SEM_OK;
 }
 
@@ -711,6 +716,8 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   if (opts->mixed && ctx->desc.lowprec == SEM_F64)
     return fail(SEM_ERR_ARG, "sem_batch_add: mixed precision needs a low-precision copy");
   if (ctx->box.N > 11) return fail(SEM_ERR_UNSUPPORTED, "sem_batch_add: batches take orders 1..11");
+  if (ctx->desc.flags != 0)
+    return fail(SEM_ERR_ARG, "sem_batch_add: batches run the default element kernels (flags must be 0)");
   int q = -1;
   for (int i = 0; i < B->max_slots; ++i)
     if (!B->ctx[i]) {

@@ -20,9 +20,25 @@ namespace {
 
 template <int N1>
 struct AxCfg {
-  // elements per work-group of the per-order kernel: about 128 threads
+  // elements per work-group of the per-order kernels: about 128 threads of
+  // one (i, j) column each
   static constexpr int EPB = (N1 * N1 >= 128) ? 1 : (128 / (N1 * N1));
   static constexpr int THREADS = N1 * N1 * EPB;
+};
+
+// The operator kernels: the same elements per work-group, AxTile<N1>::TPE
+// threads per element.
+#ifndef SEM_OP_MIN_WAVES_SPLIT
+#define SEM_OP_MIN_WAVES_SPLIT 1
+#endif
+#ifndef SEM_OP_MIN_WAVES_COL
+#define SEM_OP_MIN_WAVES_COL 1
+#endif
+template <int N1>
+struct OpCfg {
+  static constexpr int EPB = AxCfg<N1>::EPB;
+  static constexpr int THREADS = AxTile<N1>::TPE * EPB;
+  static constexpr int MIN_WAVES = AxTile<N1>::kSplit ? SEM_OP_MIN_WAVES_SPLIT : SEM_OP_MIN_WAVES_COL;
 };
 
 }  // namespace
@@ -30,12 +46,12 @@ struct AxCfg {
 namespace {
 
 template <int N1, class P, bool CG>
-__global__ void __launch_bounds__(AxCfg<N1>::THREADS)
+__global__ void __launch_bounds__(OpCfg<N1>::THREADS, OpCfg<N1>::MIN_WAVES)
     ax_kernel(int64_t E, const typename P::TC *__restrict__ Dg, const typename P::TG *__restrict__ G,
               typename P::TV *u, typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,
               const typename P::TV *__restrict__ minv, typename P::TV *__restrict__ x,
               CgState *__restrict__ st, double *__restrict__ part) {
-  using C = AxCfg<N1>;
+  using C = OpCfg<N1>;
   using TC = typename P::TC;
   __shared__ TC sD[N1 * N1];
   __shared__ TC s1[C::EPB * AxTile<N1>::TILE];
@@ -52,32 +68,30 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
                              part, sD, s1, s2, s3, sred);
 }
 
-// The low-precision operator with the D contractions on the matrix cores:
-// the per-order tile of ax_kernel, rounded up to whole waves.
-template <int N1>
-struct MfmaCfg {
-  static constexpr int EPB = AxCfg<N1>::EPB;
-  static constexpr int THREADS = (N1 * N1 * EPB + 63) / 64 * 64;
-};
-
+// The operator with the D contractions on the matrix cores (sem_ax_mfma.h):
+// ceil((N+1)^2 / 16) waves per element.
 template <int N1, class P, bool CG>
 __global__ void __launch_bounds__(MfmaCfg<N1>::THREADS)
-    ax_mfma_kernel(int64_t E, const float *__restrict__ Dg, const typename P::TG *__restrict__ G,
-                   float *u, float *__restrict__ w, const float *__restrict__ r,
-                   const float *__restrict__ minv, float *__restrict__ x, CgState *__restrict__ st,
-                   double *__restrict__ part) {
+    ax_mfma_kernel(int64_t E, const typename P::TC *__restrict__ Dg,
+                   const typename P::TG *__restrict__ G, typename P::TV *u,
+                   typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,
+                   const typename P::TV *__restrict__ minv, typename P::TV *__restrict__ x,
+                   CgState *__restrict__ st, double *__restrict__ part) {
   using C = MfmaCfg<N1>;
-  __shared__ float sD[N1 * N1];
-  __shared__ float tiles[MfmaTile<N1>::kTiles * C::EPB * AxTile<N1>::TILE];
-  __shared__ double sred[CG ? C::THREADS : 1];
+  using TC = typename P::TC;
+  __shared__ TC sD[N1 * N1];
+  __shared__ TC s1[C::EPB * AxTile<N1>::TILE];
+  __shared__ TC s2[C::EPB * AxTile<N1>::TILE];
+  __shared__ TC s3[C::EPB * AxTile<N1>::TILE];
+  __shared__ double sred[C::THREADS / 64];
   double alpha = 0.0, beta = 0.0;
   if (CG) {
-    if (st->done) return;
+    if (st->done) return;  // uniform: converged solves skip all work
     alpha = st->alpha;
     beta = st->beta;
   }
   ax_tile_mfma<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha,
-                                  beta, part, sD, tiles, sred);
+                                  beta, part, sD, s1, s2, s3, sred);
 }
 
 // Rounded copy of G for a low-precision operator.
@@ -217,7 +231,7 @@ __global__ void __launch_bounds__(AxCfg<N1>::THREADS)
 template <int N1, class P>
 hipError_t ax_dispatch(const Box &b, const void *D, const void *G, void *u, void *w, const void *r,
                        const void *minv, void *x, CgState *cg, double *part, hipStream_t s) {
-  using C = AxCfg<N1>;
+  using C = OpCfg<N1>;
   using TV = typename P::TV;
   using TG = typename P::TG;
   using TC = typename P::TC;
@@ -235,19 +249,22 @@ hipError_t ax_dispatch(const Box &b, const void *D, const void *G, void *u, void
 }
 
 template <int N1, class P>
-hipError_t mfma_dispatch(const Box &b, const float *D, const void *G, float *u, float *w,
-                         const float *r, const float *minv, float *x, CgState *cg, double *part,
-                         hipStream_t s) {
+hipError_t mfma_dispatch(const Box &b, const void *D, const void *G, void *u, void *w, const void *r,
+                         const void *minv, void *x, CgState *cg, double *part, hipStream_t s) {
   using C = MfmaCfg<N1>;
+  using TV = typename P::TV;
   using TG = typename P::TG;
+  using TC = typename P::TC;
   const int64_t blocks = (b.E() + C::EPB - 1) / C::EPB;
   if (blocks == 0) return hipSuccess;
   if (cg)
     hipLaunchKernelGGL((ax_mfma_kernel<N1, P, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
-                       b.E(), D, (const TG *)G, u, w, r, minv, x, cg, part);
+                       b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
+                       (const TV *)minv, (TV *)x, cg, part);
   else
     hipLaunchKernelGGL((ax_mfma_kernel<N1, P, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
-                       s, b.E(), D, (const TG *)G, u, w, r, minv, x, cg, part);
+                       s, b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
+                       (const TV *)minv, (TV *)x, cg, part);
   return hipGetLastError();
 }
 
@@ -284,13 +301,18 @@ int64_t ax_num_blocks(const Box &b) {
   return (b.E() + epb - 1) / epb;
 }
 
-hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
-                         const double *r, const double *minv, double *x, CgState *cg,
-                         double *part, hipStream_t s) {
+// Operator launch for precision P (class cls): the matrix-core tile or the
+// vector-unit one, by OpImpl.
+template <class P>
+hipError_t ax_launch(const Box &b, int cls, int impl, const void *D, const void *G, void *u, void *w,
+                     const void *r, const void *minv, void *x, CgState *cg, double *part,
+                     hipStream_t s) {
+  const bool mfma = impl == kImplMfma || (impl == kImplDefault && op_uses_mfma(cls, b.N));
   switch (b.N) {
-#define CASE(n) \
-  case n:       \
-    return ax_dispatch<n + 1, PrecF64>(b, D, G, u, w, r, minv, x, cg, part, s);
+#define CASE(n)                                                                      \
+  case n:                                                                            \
+    return mfma ? mfma_dispatch<n + 1, P>(b, D, G, u, w, r, minv, x, cg, part, s)   \
+                : ax_dispatch<n + 1, P>(b, D, G, u, w, r, minv, x, cg, part, s);
     SEM_FOR_EACH_ORDER(CASE)
 #undef CASE
     default:
@@ -298,53 +320,17 @@ hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double 
   }
 }
 
-hipError_t launch_ax_lowp(const Box &b, int prec, int mfma, const float *D, const void *G, float *u,
+hipError_t launch_ax_f64(const Box &b, int impl, const double *D, const double *G, double *u,
+                         double *w, const double *r, const double *minv, double *x, CgState *cg,
+                         double *part, hipStream_t s) {
+  return ax_launch<PrecF64>(b, 0, impl, D, G, u, w, r, minv, x, cg, part, s);
+}
+
+hipError_t launch_ax_lowp(const Box &b, int prec, int impl, const float *D, const void *G, float *u,
                           float *w, const float *r, const float *minv, float *x, CgState *cg,
                           double *part, hipStream_t s) {
-  if (mfma && prec == SEM_F32) {
-    switch (b.N) {
-#define CASE(n) \
-  case n:       \
-    return mfma_dispatch<n + 1, PrecF32>(b, D, G, u, w, r, minv, x, cg, part, s);
-      SEM_FOR_EACH_ORDER(CASE)
-#undef CASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  if (mfma && prec == SEM_BF16) {
-    switch (b.N) {
-#define CASE(n) \
-  case n:       \
-    return mfma_dispatch<n + 1, PrecBF16>(b, D, G, u, w, r, minv, x, cg, part, s);
-      SEM_FOR_EACH_ORDER(CASE)
-#undef CASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  if (prec == SEM_F32) {
-    switch (b.N) {
-#define CASE(n) \
-  case n:       \
-    return ax_dispatch<n + 1, PrecF32>(b, D, G, u, w, r, minv, x, cg, part, s);
-      SEM_FOR_EACH_ORDER(CASE)
-#undef CASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
-  if (prec == SEM_BF16) {
-    switch (b.N) {
-#define CASE(n) \
-  case n:       \
-    return ax_dispatch<n + 1, PrecBF16>(b, D, G, u, w, r, minv, x, cg, part, s);
-      SEM_FOR_EACH_ORDER(CASE)
-#undef CASE
-      default:
-        return hipErrorInvalidValue;
-    }
-  }
+  if (prec == SEM_F32) return ax_launch<PrecF32>(b, 1, impl, D, G, u, w, r, minv, x, cg, part, s);
+  if (prec == SEM_BF16) return ax_launch<PrecBF16>(b, 2, impl, D, G, u, w, r, minv, x, cg, part, s);
   return hipErrorInvalidValue;
 }
 

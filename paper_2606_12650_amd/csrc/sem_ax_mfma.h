@@ -1,22 +1,33 @@
-// The low-precision element operator with its D contractions on the matrix
-// cores (gfx950 MFMA, FP32 accumulation): the same tile contract as ax_tile
-// (sem_ax_tile.h) for PrecF32 and PrecBF16.
+// The element operator with its D contractions on the matrix cores (gfx950
+// MFMA): the same tile contract as ax_tile (sem_ax_tile.h) for PrecF64
+// (v_mfma_f64_16x16x4f64), PrecF32 (v_mfma_f32_16x16x4f32) and PrecBF16
+// (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation).
 //
 // Each directional contraction of an element is a GEMM
 //     C[m][n] = sum_c A[m][c] B[c][n]
-// with A = D (gradient) or D^T (transposed contraction), c the contracted
-// 1-D index, m the output 1-D index (N+1 of the 16 MFMA rows) and n a pair of
-// the two other indices (N1*N1 pairs, 16 per MFMA column tile).  FP32 uses
-// v_mfma_f32_16x16x4f32 over ceil(N1/4) steps of K, BF16 one
-// v_mfma_f32_16x16x32_bf16 (K padded with zeros).  Operand B and the results
-// go through LDS; the metric product between the two contractions and the
-// final sum of the three directions run one thread per (i, j) column as in
-// ax_tile.  Work-groups must be whole waves (MFMA runs on all 64 lanes).
+// with A = D (gradient) or D^T (divergence), c the contracted 1-D index, m the
+// output 1-D index (N+1 of the 16 MFMA rows) and n a pair of the two other
+// indices: N+1 squared pairs in column tiles of 16.  An element has
+// ceil((N+1)^2 / 16) waves; wave w of an element takes column tile w of all
+// three directions.
 //
-// Lane layouts of the two instructions (lane l of the wave):
-//   A[m][c]: m = l % 16, c = 4 s + l / 16 (f32, step s) or 8 (l / 16) + q (bf16)
-//   B[c][n]: c as for A, n = l % 16
-//   C[m][n] in result register v: m = 4 (l / 16) + v, n = l % 16
+// The element's nodes are owned in the layout of the t-direction result: lane
+// l of wave w holds the nodes (i, j, k) with i + (N+1) j = 16 w + l % 16 and k
+// one of the four result rows of its lane group.  HBM accesses in that layout
+// are 16 consecutive values per lane group and k-plane.  Per element:
+//   prologue: load the operand (CG: update x and p first) and G into
+//             registers, operand to LDS tile U
+//   gradient: r and s results to LDS tiles R and S, t result in registers
+//   metric:   at the owned nodes (G from registers), the weighted gradient
+//             back to R, S and U (U is no longer read)
+//   divergence: r and s in place in R and S (a wave reads and writes only
+//             its own column tile's pairs), t in registers
+//   result:   w = (R + S) + t part at the owned nodes, stored to HBM.
+//
+// Lane layouts of the three instructions (lane l, g = l / 16):
+//   f64/f32 16x16x4 step s: A[m = l % 16][c = 4 s + g], B[c = 4 s + g][n = l % 16]
+//   bf16 16x16x16:          A[m = l % 16][c = 4 g + q], B[c = 4 g + q][n = l % 16]
+//   result register v:      f64: m = 4 v + g;  f32 and bf16: m = 4 g + v;  n = l % 16
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,199 +38,303 @@
 
 namespace semk {
 
+typedef double mfma_v4d __attribute__((ext_vector_type(4)));
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 mfma_v8bf __attribute__((ext_vector_type(8)));
+typedef short mfma_v4s __attribute__((ext_vector_type(4)));
 
 template <int N1>
 struct MfmaTile {
   static_assert(N1 <= 16, "one MFMA row block per 1-D index");
-  static constexpr int PAIRS = N1 * N1;
-  static constexpr int NT = (PAIRS + 15) / 16;  // column tiles per contraction
-  static constexpr int KS = (N1 + 3) / 4;       // f32 K steps
-  static constexpr int kTiles = 6;              // LDS tiles per element
+  static constexpr int PL = N1 * N1;
+  static constexpr int NT = (PL + 15) / 16;  // column tiles = waves per element
+  static constexpr int KS = (N1 + 3) / 4;    // 16x16x4 steps
+  static constexpr int kTiles = 3;           // LDS tiles per element: U, R, S
 };
 
-// LDS offset of the point with contracted/output index c and pair index q in
-// direction d (0: r contracts i, 1: s contracts j, 2: t contracts k).
+// Work-group of the matrix-core operator: EPB elements of NT waves each
+// (about eight waves per work-group).
+template <int N1>
+struct MfmaCfg {
+  static constexpr int NT = MfmaTile<N1>::NT;
+  static constexpr int EPB = NT >= 8 ? 1 : 8 / NT;
+  static constexpr int THREADS = 64 * NT * EPB;
+};
+
+template <class P>
+struct MfmaOps {
+  using Acc = mfma_v4f;
+  static constexpr bool kF64 = false;
+};
+template <>
+struct MfmaOps<PrecF64> {
+  using Acc = mfma_v4d;
+  static constexpr bool kF64 = true;
+};
+
+// Result row of register v in lane group g.
+template <class P>
+__device__ __forceinline__ int mfma_row(int g, int v) {
+  return MfmaOps<P>::kF64 ? 4 * v + g : 4 * g + v;
+}
+
+// LDS offset of the node with contracted/result index c and pair index q in
+// direction d (0: r, c = i; 1: s, c = j; 2: t, c = k).
 template <int N1>
 __device__ __forceinline__ int mfma_point(int d, int c, int q) {
   using T = AxTile<N1>;
   const int a = q % N1, b = q / N1;
-  int i, j, k;
-  if (d == 0) { i = c; j = a; k = b; }
-  else if (d == 1) { j = c; i = a; k = b; }
-  else { k = c; i = a; j = b; }
+  const int i = d == 0 ? c : a;
+  const int j = d == 1 ? c : (d == 0 ? a : b);
+  const int k = d == 2 ? c : b;
   return k * T::PLANE + j * T::P + i;
 }
 
-// One column tile of one directional contraction of one element:
-// out(point) = sum_c Dm[m][c] in(point(c, q)) for the tile's 16 pairs.
-// transpose = false: Dm = D (gradient); true: Dm = D^T.
+__device__ __forceinline__ short mfma_bf16_bits(float v) {
+  return (short)(__float_as_uint(v) >> 16);  // exact: v is a bfloat16 value
+}
+
+// The A operand of one lane: D (transpose = false) or D^T, zero-padded.
 template <int N1, class P>
-__device__ __forceinline__ void mfma_contract(const typename P::TC *sD, const float *in, float *out,
-                                              int d, int tile, bool transpose) {
-  using M = MfmaTile<N1>;
-  const int l = threadIdx.x & 63;
-  const int n = l & 15;
-  const int q = tile * 16 + n;  // pair index of this lane's column
-  const bool qok = q < M::PAIRS;
-  mfma_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  const int m = l & 15;
-  if constexpr (P::kBf16) {
-    mfma_v8bf a, b;
+struct MfmaA {
+  using TC = typename P::TC;
+  TC a[P::kBf16 ? 1 : MfmaTile<N1>::KS];
+  mfma_v4s ab;
+  __device__ __forceinline__ void load(const TC *sD, bool transpose) {
+    const int l = threadIdx.x & 63;
+    const int m = l & 15, g = l >> 4;
+    if constexpr (P::kBf16) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int c = 8 * (l >> 4) + s;
-      const bool cok = c < N1;
-      const float av = (m < N1 && cok) ? (float)(transpose ? sD[c * N1 + m] : sD[m * N1 + c]) : 0.0f;
-      const float bv = (qok && cok) ? in[mfma_point<N1>(d, c, q)] : 0.0f;
-      a[s] = (__bf16)av;  // exact: D and the operand are bfloat16 values already
-      b[s] = (__bf16)bv;
+      for (int q = 0; q < 4; ++q) {
+        const int c = 4 * g + q;
+        const float v = (m < N1 && c < N1) ? (transpose ? sD[c * N1 + m] : sD[m * N1 + c]) : 0.0f;
+        ab[q] = mfma_bf16_bits(v);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < MfmaTile<N1>::KS; ++s) {
+        const int c = 4 * s + g;
+        a[s] = (m < N1 && c < N1) ? (transpose ? sD[c * N1 + m] : sD[m * N1 + c]) : (TC)0;
+      }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+};
+
+// Column tile `tile` of direction d: the four result rows of this lane for
+// pair q = 16 tile + l % 16, from the LDS tile `in`.
+template <int N1, class P>
+__device__ __forceinline__ typename MfmaOps<P>::Acc mfma_contract(const MfmaA<N1, P> &A,
+                                                                 const typename P::TC *in, int d,
+                                                                 int tile) {
+  using M = MfmaTile<N1>;
+  using TC = typename P::TC;
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4;
+  const int q = tile * 16 + (l & 15);
+  const bool qok = q < M::PL;
+  typename MfmaOps<P>::Acc acc = {0, 0, 0, 0};
+  if constexpr (P::kBf16) {
+    mfma_v4s b;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = 4 * g + u;
+      const bool ok = qok && c < N1;
+      const float v = in[ok ? mfma_point<N1>(d, c, q) : 0];
+      b[u] = mfma_bf16_bits(ok ? v : 0.0f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A.ab, b, acc, 0, 0, 0);
   } else {
+    TC b[M::KS];
 #pragma unroll
     for (int s = 0; s < M::KS; ++s) {
-      const int c = 4 * s + (l >> 4);
-      const bool cok = c < N1;
-      const float av = (m < N1 && cok) ? (float)(transpose ? sD[c * N1 + m] : sD[m * N1 + c]) : 0.0f;
-      const float bv = (qok && cok) ? in[mfma_point<N1>(d, c, q)] : 0.0f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+      const int c = 4 * s + g;
+      const bool ok = qok && c < N1;
+      const TC v = in[ok ? mfma_point<N1>(d, c, q) : 0];
+      b[s] = ok ? v : (TC)0;
+    }
+#pragma unroll
+    for (int s = 0; s < M::KS; ++s) {
+      if constexpr (MfmaOps<P>::kF64)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A.a[s], b[s], acc, 0, 0, 0);
+      else
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.a[s], b[s], acc, 0, 0, 0);
+    }
+  }
+  return acc;
+}
+
+// Store the lane's result rows of a column tile to `out` (rows < N1 only).
+template <int N1, class P>
+__device__ __forceinline__ void mfma_store(typename P::TC *out, const typename MfmaOps<P>::Acc &acc,
+                                           int d, int tile) {
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4;
+  const int q = tile * 16 + (l & 15);
+  if (q >= MfmaTile<N1>::PL) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = mfma_row<P>(g, v);
+    if (m < N1) out[mfma_point<N1>(d, m, q)] = (typename P::TC)acc[v];
+  }
+}
+
+// Same contract as ax_tile<N1, EPB, P, CG> with blockDim = MfmaCfg<N1>::THREADS
+// (EPB = MfmaCfg<N1>::EPB).  LDS: sD N1*N1 TC, s1/s2/s3 EPB * AxTile<N1>::TILE
+// TC each, sred blockDim / 64 doubles.
+template <int N1, int EPB, class P, bool CG>
+__device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
+                                             const typename P::TG *__restrict__ G, typename P::TV *u,
+                                             typename P::TV *__restrict__ w,
+                                             const typename P::TV *__restrict__ r,
+                                             const typename P::TV *__restrict__ minv,
+                                             typename P::TV *__restrict__ x, double alpha_d,
+                                             double beta_d, double *__restrict__ part_el,
+                                             typename P::TC *sD, typename P::TC *s1,
+                                             typename P::TC *s2, typename P::TC *s3,
+                                             double *sred) {
+  using T = AxTile<N1>;
+  using M = MfmaTile<N1>;
+  using TV = typename P::TV;
+  using TC = typename P::TC;
+  using Acc = typename MfmaOps<P>::Acc;
+  constexpr int NP = T::NP;
+  constexpr int PL = M::PL;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int el = wave / M::NT;
+  const int tile = wave - el * M::NT;  // this wave's column tile in every direction
+  const int l = tid & 63;
+  const int g = l >> 4;
+  const int q = tile * 16 + (l & 15);  // owned pair = i + N1 j
+  const int64_t e = e0 + el;
+  const bool mine = el < EPB;
+  const bool active = mine && e < E && q < PL;
+  const int slot = mine ? el : 0;
+  TC *U = s1 + slot * T::TILE;
+  TC *R = s2 + slot * T::TILE;
+  TC *S = s3 + slot * T::TILE;
+  const int qi = q % N1, qj = q / N1;
+
+  for (int t = tid; t < N1 * N1; t += blockDim.x) sD[t] = Dg[t];
+
+  // prologue at the owned nodes (k = result row v of this lane group).  Every
+  // load is issued unconditionally (lanes that own no node read entry 0 and
+  // drop the value) so that all of them are in flight together; only the
+  // stores are predicated.
+  const int64_t base = e * NP + q;
+  TC uk[4], gk[4][6];
+  int64_t idx[4];
+  bool okv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = mfma_row<P>(g, v);
+    okv[v] = active && k < N1;
+    idx[v] = okv[v] ? base + (int64_t)k * PL : 0;
+  }
+  // all loads first (one round trip), then the updates and their stores
+  TV pv[4], xv[4], mv[4], rv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    pv[v] = ld_once(u + idx[v]);
+    if (CG) {
+      xv[v] = ld_once(x + idx[v]);
+      mv[v] = ld_once(minv + idx[v]);
+      rv[v] = ld_once(r + idx[v]);
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int mo = 4 * (l >> 4) + v;
-    if (mo < N1 && qok) out[mfma_point<N1>(d, mo, q)] = acc[v];
+    const int64_t gi = okv[v] ? (e * 6 * NP + (int64_t)(idx[v] - e * NP)) : 0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gk[v][c] = load_g<P>(G + gi + (okv[v] ? (int64_t)c * NP : 0));
   }
-}
-
-// Same contract as ax_tile<N1, EPB, P, CG> (P = PrecF32 or PrecBF16) with
-// blockDim a multiple of 64.  LDS: sD N1*N1 TC, tiles 6 * EPB * TILE floats,
-// sred blockDim doubles.
-template <int N1, int EPB, class P, bool CG>
-__device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
-                                             const typename P::TG *__restrict__ G, float *u,
-                                             float *__restrict__ w, const float *__restrict__ r,
-                                             const float *__restrict__ minv, float *__restrict__ x,
-                                             double alpha_d, double beta_d,
-                                             double *__restrict__ part_el, float *sD, float *tiles,
-                                             double *sred) {
-  static_assert(sizeof(typename P::TC) == 4, "MFMA operator is for the FP32 / BF16 modes");
-  using T = AxTile<N1>;
-  using M = MfmaTile<N1>;
-  constexpr int NP = T::NP;
-  constexpr int PL = N1 * N1;
-  const int tid = threadIdx.x;
-  const int el = tid / PL;
-  const int ij = tid - el * PL;
-  const int i = ij % N1;
-  const int j = ij / N1;
-  const int64_t e = e0 + el;
-  const bool active = el < EPB && e < E;
-  const int slot = el < EPB ? el : 0;
-  float *U = tiles + (slot * 6 + 0) * T::TILE;
-  float *R = tiles + (slot * 6 + 1) * T::TILE;
-  float *S = tiles + (slot * 6 + 2) * T::TILE;
-  float *Tt = tiles + (slot * 6 + 3) * T::TILE;
-  float *X1 = tiles + (slot * 6 + 4) * T::TILE;
-  float *X2 = tiles + (slot * 6 + 5) * T::TILE;
-
-  for (int t = tid; t < N1 * N1; t += blockDim.x) sD[t] = Dg[t];
-
-  // prologue and operand, one thread per (i, j) column
-  const int64_t base = e * NP + ij;
-  float uk[N1];
-  if (active) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    TV val = pv[v];
     if (CG) {
-      const float beta = (float)beta_d, alpha = (float)alpha_d;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        const int64_t idx = base + k * PL;
-        const float pold = ld_once(u + idx);
-        st_once(x + idx, ld_once(x + idx) + alpha * pold);
-        const float v = ld_once(minv + idx) * ld_once(r + idx) + beta * pold;
-        uk[k] = v;
-        st_once(u + idx, v);
+      const TV xn = xv[v] + (TV)alpha_d * pv[v];
+      val = mv[v] * rv[v] + (TV)beta_d * pv[v];
+      if (okv[v]) {
+        st_once(x + idx[v], xn);
+        st_once(u + idx[v], val);
       }
-    } else {
-#pragma unroll
-      for (int k = 0; k < N1; ++k) uk[k] = ld_once(u + base + k * PL);
     }
-  } else {
+    uk[v] = okv[v] ? (TC)val : (TC)0;
 #pragma unroll
-    for (int k = 0; k < N1; ++k) uk[k] = 0.0f;
+    for (int c = 0; c < 6; ++c) gk[v][c] = okv[v] ? gk[v][c] : (TC)0;
   }
-  if (el < EPB) {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) U[k * T::PLANE + j * T::P + i] = contraction_input<P>(uk[k]);
-  }
-  __syncthreads();
-
-  // gradient: 3 directions x NT column tiles per element, spread over waves
-  const int nwaves = blockDim.x >> 6;
-  const int wave = tid >> 6;
-  constexpr int ITEMS = EPB * 3 * M::NT;
-  for (int it = wave; it < ITEMS; it += nwaves) {
-    const int es = it / (3 * M::NT);
-    const int d = (it / M::NT) % 3;
-    const int tile = it % M::NT;
-    float *in = tiles + (es * 6 + 0) * T::TILE;
-    float *out = tiles + (es * 6 + 1 + d) * T::TILE;
-    mfma_contract<N1, P>((const typename P::TC *)sD, in, out, d, tile, false);
+  for (int v = 0; v < 4; ++v) {
+    const int k = mfma_row<P>(g, v);
+    if (mine && k < N1 && q < PL) U[k * T::PLANE + qj * T::P + qi] = contraction_input<P>(uk[v]);
   }
   __syncthreads();
 
-  // metric product at each node of the column (the weighted gradient is
-  // rounded to bfloat16 in that mode, as it feeds the next contraction)
-  const typename P::TG *Ge = G + (active ? e : 0) * 6 * NP + ij;
-  if (el < EPB) {
+  // gradient
+  MfmaA<N1, P> A;
+  A.load(sD, false);
+  Acc ut = {0, 0, 0, 0};
+  if (mine) {
+    const Acc ur = mfma_contract<N1, P>(A, U, 0, tile);
+    const Acc us = mfma_contract<N1, P>(A, U, 1, tile);
+    ut = mfma_contract<N1, P>(A, U, 2, tile);
+    mfma_store<N1, P>(R, ur, 0, tile);
+    mfma_store<N1, P>(S, us, 1, tile);
+  }
+  __syncthreads();
+
+  // metric at the owned nodes; the weighted gradient is the next contraction's input
+  if (mine && q < PL) {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      const int o = k * T::PLANE + j * T::P + i;
-      float gk[6];
-#pragma unroll
-      for (int qq = 0; qq < 6; ++qq) gk[qq] = active ? load_g<P>(Ge + qq * NP + k * PL) : 0.0f;
-      const float ur = R[o], us = S[o], ut = Tt[o];
-      R[o] = contraction_input<P>(gk[0] * ur + gk[1] * us + gk[2] * ut);
-      S[o] = contraction_input<P>(gk[1] * ur + gk[3] * us + gk[4] * ut);
-      Tt[o] = contraction_input<P>(gk[2] * ur + gk[4] * us + gk[5] * ut);
+    for (int v = 0; v < 4; ++v) {
+      const int k = mfma_row<P>(g, v);
+      if (k < N1) {
+        const int o = k * T::PLANE + qj * T::P + qi;
+        const TC ur = R[o], us = S[o], utv = (TC)ut[v];
+        R[o] = contraction_input<P>(gk[v][0] * ur + gk[v][1] * us + gk[v][2] * utv);
+        S[o] = contraction_input<P>(gk[v][1] * ur + gk[v][3] * us + gk[v][4] * utv);
+        U[o] = contraction_input<P>(gk[v][2] * ur + gk[v][4] * us + gk[v][5] * utv);
+      }
     }
   }
   __syncthreads();
 
-  // transposed contractions: r -> U, s -> X1, t -> X2
-  for (int it = wave; it < ITEMS; it += nwaves) {
-    const int es = it / (3 * M::NT);
-    const int d = (it / M::NT) % 3;
-    const int tile = it % M::NT;
-    float *in = tiles + (es * 6 + 1 + d) * T::TILE;
-    float *out = tiles + (es * 6 + (d == 0 ? 0 : 3 + d)) * T::TILE;
-    mfma_contract<N1, P>((const typename P::TC *)sD, in, out, d, tile, true);
+  // divergence: r and s in place (own column tile), t in registers
+  A.load(sD, true);
+  Acc wt = {0, 0, 0, 0};
+  if (mine) {
+    const Acc vr = mfma_contract<N1, P>(A, R, 0, tile);
+    const Acc vs = mfma_contract<N1, P>(A, S, 1, tile);
+    wt = mfma_contract<N1, P>(A, U, 2, tile);
+    mfma_store<N1, P>(R, vr, 0, tile);
+    mfma_store<N1, P>(S, vs, 1, tile);
   }
   __syncthreads();
 
   double acc = 0.0;
+  if (mine && q < PL) {
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    const int o = k * T::PLANE + j * T::P + i;
-    const float v = (U[o] + X1[o]) + X2[o];
-    if (active) w[base + k * PL] = v;
-    acc += (double)uk[k] * (double)v;
+    for (int v = 0; v < 4; ++v) {
+      const int k = mfma_row<P>(g, v);
+      if (k < N1) {
+        const int o = k * T::PLANE + qj * T::P + qi;
+        const TC val = (R[o] + S[o]) + (TC)wt[v];
+        if (active) w[base + (int64_t)k * PL] = (TV)val;
+        acc += (double)uk[v] * (double)val;
+      }
+    }
   }
   if (CG) {
-    sred[tid] = acc;
+    // per-element sum of p.(A_L p): wave sums, then the element's waves in order
+    acc = wave_sum(acc);
+    if (l == 0) sred[wave] = acc;
     __syncthreads();
-    constexpr int P2 = next_pow2(PL);
-    const int lt = ij;
-#pragma unroll
-    for (int s = P2 / 2; s > 0; s >>= 1) {
-      if (el < EPB && lt < s && lt + s < PL) sred[tid] += sred[tid + s];
-      __syncthreads();
+    if (mine && tile == 0 && l == 0 && e < E) {
+      double s = 0.0;
+      for (int t = 0; t < M::NT; ++t) s += sred[el * M::NT + t];
+      part_el[e] = s;
     }
-    if (active && lt == 0) part_el[e] = sred[tid];
   }
-  __syncthreads();
+  __syncthreads();  // LDS is free for the next tile
 }
 
 }  // namespace semk

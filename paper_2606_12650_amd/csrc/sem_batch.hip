@@ -26,6 +26,7 @@
 #include <map>
 #include <mutex>
 
+#include "sem_ax_mfma.h"
 #include "sem_ax_tile.h"
 #include "sem_cg_dev.h"
 #include "sem_device.h"
@@ -37,13 +38,16 @@ namespace {
 
 constexpr int kSchedThreads = 1024;
 
-// Operator tiles compiled for batches (order, elements per work-group): the
-// single-solve kernel's tile and twice that where the FP64 LDS stays within
-// 64 KiB.
-#define SEM_BATCH_TILES(X)                                                    \
+// Operator tiles compiled for batches (order, elements per work-group).  An
+// order uses the vector-unit tiles or the matrix-core ones of its class, as
+// its single solves do (op_uses_mfma): the single-solve tile first, then a
+// larger one where the FP64 LDS stays within 64 KiB and the work-group within
+// 512 (vector) or 1024 (matrix-core) threads.
+#define SEM_BATCH_TILES_VALU(X)                                               \
   X(1, 32) X(1, 64) X(2, 14) X(2, 28) X(3, 8) X(3, 16) X(4, 5) X(4, 10)      \
   X(5, 3) X(5, 6) X(6, 2) X(6, 4) X(7, 2) X(7, 4) X(8, 1) X(8, 2) X(9, 1)   \
   X(9, 2) X(10, 1) X(11, 1)
+#define SEM_BATCH_TILES_MFMA(X) X(7, 2) X(7, 4) X(8, 1) X(8, 2) X(9, 1) X(10, 1) X(11, 1)
 
 template <int CLS>
 struct ClassPrec;
@@ -59,10 +63,17 @@ template <>
 struct ClassPrec<2> {
   using P = PrecBF16;
 };
+template <>
+struct ClassPrec<3> {
+  using P = PrecF64;
+};
 
-template <int N1, int EPB>
+template <int N1, int EPB, bool MFMA>
 struct OpCfg {
-  static constexpr int THREADS = (N1 * N1 * EPB + 63) / 64 * 64;
+  static constexpr int THREADS =
+      MFMA ? 64 * MfmaTile<N1>::NT * EPB : (AxTile<N1>::TPE * EPB + 63) / 64 * 64;
+  static constexpr int kTiles = MFMA ? 3 : AxTile<N1>::kTiles;
+  static constexpr int SRED = MFMA ? THREADS / 64 : THREADS;
 };
 
 // Largest k in [0, cnt) with pre[k] <= w, for 1 <= cnt <= 4096 and
@@ -112,7 +123,7 @@ __device__ inline int slot_bin(const BatchSlot &S) {
   if (S.mixed == 0) {
     if (S.phase == kPhaseFp64 && S.st->done == kRunning) cls = 0;
   } else if (S.phase == kPhaseOuterOp) {
-    cls = 0;
+    cls = 3;
   } else if (S.phase == kPhaseInner && S.st_in->done == kRunning) {
     cls = S.mixed == SEM_F32 ? 1 : 2;
   }
@@ -129,7 +140,8 @@ __global__ void __launch_bounds__(kSchedThreads)
     const BatchSlot &S = slots[q];
     const int b = slot_bin(S);
     s_bin[q] = b;
-    s_cnt[q] = b < 0 ? 0 : (int)((S.E + tiles.epb[S.N] - 1) / tiles.epb[S.N]);
+    const int epb = b < 0 ? 1 : tiles.epb[b / kBatchOrders][S.N];
+    s_cnt[q] = b < 0 ? 0 : (int)((S.E + epb - 1) / epb);
     s_vt[q] = (S.active && S.phase != kPhaseFinished) ? S.vtiles : 0;
   }
   __syncthreads();
@@ -167,44 +179,68 @@ __global__ void __launch_bounds__(kSchedThreads)
 
 // ------------------------------------------------------------- operator
 
-template <int N1, int EPB, int CLS>
-__global__ void __launch_bounds__((OpCfg<N1, EPB>::THREADS))
+// The element tile of a batched operator item: the matrix-core one or the
+// vector-unit one, as the single solves of this class and order run.
+template <int N1, int EPB, class P, bool CG, bool MFMA>
+__device__ __forceinline__ void batch_tile(int64_t E, int64_t e0, const typename P::TC *D,
+                                           const typename P::TG *G, typename P::TV *u,
+                                           typename P::TV *w, const typename P::TV *r,
+                                           const typename P::TV *minv, typename P::TV *x,
+                                           double alpha, double beta, double *part,
+                                           typename P::TC *sD, typename P::TC *s1,
+                                           typename P::TC *s2, typename P::TC *s3, double *sred) {
+  if constexpr (MFMA)
+    ax_tile_mfma<N1, EPB, P, CG>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3,
+                                 sred);
+  else
+    ax_tile<N1, EPB, P, CG>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3, sred);
+}
+
+template <int N1, int EPB, int CLS, bool MFMA>
+__global__ void __launch_bounds__((OpCfg<N1, EPB, MFMA>::THREADS))
     batch_op_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int bin) {
   using P = typename ClassPrec<CLS>::P;
   using TC = typename P::TC;
   using T = AxTile<N1>;
+  using C = OpCfg<N1, EPB, MFMA>;
+  static_assert((int)sizeof(TC) * (N1 * N1 + C::kTiles * EPB * T::TILE) + 8 * C::SRED <= 64 * 1024,
+                "batched operator tile exceeds 64 KiB of LDS");
+  static_assert(C::THREADS <= (MFMA ? 1024 : 512), "batched operator tile exceeds its work-group");
   __shared__ TC sD[N1 * N1];
   __shared__ TC s1[EPB * T::TILE];
   __shared__ TC s2[EPB * T::TILE];
-  __shared__ TC s3[T::kTiles == 3 ? EPB * T::TILE : 1];
-  __shared__ double sred[OpCfg<N1, EPB>::THREADS];
+  __shared__ TC s3[C::kTiles == 3 ? EPB * T::TILE : 1];
+  __shared__ double sred[C::SRED];
   const int cnt = sc.meta[2 * bin], total = sc.meta[2 * bin + 1];
   int w0, w1;
   block_range(total, &w0, &w1);
   if (w0 >= w1) return;
   const int *pre = sc.prefix + bin * (sc.max_slots + 1);
   const int *sl = sc.slot + bin * sc.max_slots;
-  int k = find_slot(pre, cnt, w0);
-  int first = pre[k], next = pre[k + 1];
+  // the walk is uniform over the work-group: keep it in scalar registers
+  int k = __builtin_amdgcn_readfirstlane(find_slot(pre, cnt, w0));
+  int first = __builtin_amdgcn_readfirstlane(pre[k]);
+  int next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
+#pragma unroll 1
   for (int w = w0; w < w1; ++w) {
     while (w >= next) {
       ++k;
       first = next;
-      next = pre[k + 1];
+      next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
     }
-    const BatchSlot &S = slots[sl[k]];
+    const BatchSlot &S = slots[__builtin_amdgcn_readfirstlane(sl[k])];
     const int64_t e0 = (int64_t)(w - first) * EPB;
     if constexpr (CLS == 0) {
-      if (S.mixed == 0)
-        ax_tile<N1, EPB, PrecF64, true>(S.E, e0, S.D, S.G, S.p, S.w, S.r, S.minv, S.x, S.st->alpha,
-                                        S.st->beta, S.part_el, sD, s1, s2, s3, sred);
-      else  // true-residual operator of a mixed solve's outer step
-        ax_tile<N1, EPB, PrecF64, false>(S.E, e0, S.D, S.G, S.x, S.w, nullptr, nullptr, nullptr,
-                                         0.0, 0.0, S.part_el, sD, s1, s2, s3, sred);
+      batch_tile<N1, EPB, PrecF64, true, MFMA>(S.E, e0, S.D, S.G, S.p, S.w, S.r, S.minv, S.x,
+                                               S.st->alpha, S.st->beta, S.part_el, sD, s1, s2, s3,
+                                               sred);
+    } else if constexpr (CLS == 3) {  // true-residual operator of a mixed solve's outer step
+      batch_tile<N1, EPB, PrecF64, false, MFMA>(S.E, e0, S.D, S.G, S.x, S.w, nullptr, nullptr,
+                                                nullptr, 0.0, 0.0, S.part_el, sD, s1, s2, s3, sred);
     } else {
-      ax_tile<N1, EPB, P, true>(S.E, e0, S.Dlo, (const typename P::TG *)S.Glo, S.pin, S.win, S.rin,
-                                S.minv32, S.e, S.st_in->alpha, S.st_in->beta, S.part_el, sD, s1,
-                                s2, s3, sred);
+      batch_tile<N1, EPB, P, true, MFMA>(S.E, e0, S.Dlo, (const typename P::TG *)S.Glo, S.pin,
+                                         S.win, S.rin, S.minv32, S.e, S.st_in->alpha,
+                                         S.st_in->beta, S.part_el, sD, s1, s2, s3, sred);
     }
   }
 }
@@ -274,15 +310,18 @@ __global__ void __launch_bounds__(kVecThreads)
   if (w0 >= w1) return;
   const int *pre = sc.prefix + kBatchBins * (sc.max_slots + 1);
   const int *sl = sc.slot + kBatchBins * sc.max_slots;
-  int k = find_slot(pre, cnt, w0);
-  int first = pre[k], next = pre[k + 1];
+  // the walk is uniform over the work-group: keep it in scalar registers
+  int k = __builtin_amdgcn_readfirstlane(find_slot(pre, cnt, w0));
+  int first = __builtin_amdgcn_readfirstlane(pre[k]);
+  int next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
+#pragma unroll 1
   for (int w = w0; w < w1; ++w) {
     while (w >= next) {
       ++k;
       first = next;
-      next = pre[k + 1];
+      next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
     }
-    const BatchSlot &S = slots[sl[k]];
+    const BatchSlot &S = slots[__builtin_amdgcn_readfirstlane(sl[k])];
     const int tile = w - first;
     switch (S.N) {
 #define VCASE(n_)                                \
@@ -371,8 +410,8 @@ __global__ void __launch_bounds__(kFinThreads)
 // Resident work-groups of each persistent kernel on a device: the occupancy
 // the compiler's resource use allows, times the compute units.
 struct BatchGrids {
-  int op[kBatchClasses][kBatchOrders + 1][2];  // [class][order][tile: base, doubled]
-  int vec[2];                                  // update, finish
+  int op[kBatchClasses][kBatchOrders + 1][65];  // [class][order][elements per item]
+  int vec[2];                                   // update, finish
 };
 std::mutex g_grid_mu;
 std::map<int, BatchGrids> g_grids;
@@ -387,8 +426,6 @@ int resident_blocks(K kernel, int threads, int cus) {
   return per_cu * cus;
 }
 
-int tile_index(int N, int epb) { return epb == batch_default_epb(N) ? 0 : 1; }
-
 const BatchGrids *current_grids() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
@@ -397,32 +434,60 @@ const BatchGrids *current_grids() {
   return it == g_grids.end() ? nullptr : &it->second;
 }
 
-template <int N1, int EPB>
-hipError_t launch_op(int cls, const BatchGrids &g, const BatchSlot *slots, const BatchSched &sc,
-                     int bin, hipStream_t s) {
-  const int grid = g.op[cls][N1 - 1][tile_index(N1 - 1, EPB)];
-  const dim3 threads(OpCfg<N1, EPB>::THREADS);
-  if (cls == 0)
-    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 0>), dim3(grid), threads, 0, s, slots, sc, bin);
-  else if (cls == 1)
-    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 1>), dim3(grid), threads, 0, s, slots, sc, bin);
-  else
-    hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 2>), dim3(grid), threads, 0, s, slots, sc, bin);
-  return hipSuccess;
+// Grid sizes of the operator kernels of one tile in every class that runs it.
+template <int N1, int EPB, bool MFMA>
+void fill_grid(BatchGrids &g, int cus) {
+  constexpr int N = N1 - 1;
+  constexpr int T = OpCfg<N1, EPB, MFMA>::THREADS;
+  if constexpr (op_uses_mfma(0, N) == MFMA)
+    g.op[0][N][EPB] = resident_blocks(batch_op_kernel<N1, EPB, 0, MFMA>, T, cus);
+  if constexpr (op_uses_mfma(1, N) == MFMA)
+    g.op[1][N][EPB] = resident_blocks(batch_op_kernel<N1, EPB, 1, MFMA>, T, cus);
+  if constexpr (op_uses_mfma(2, N) == MFMA)
+    g.op[2][N][EPB] = resident_blocks(batch_op_kernel<N1, EPB, 2, MFMA>, T, cus);
+  if constexpr (op_uses_mfma(3, N) == MFMA)
+    g.op[3][N][EPB] = resident_blocks(batch_op_kernel<N1, EPB, 3, MFMA>, T, cus);
+}
+
+template <int N1, int EPB, bool MFMA>
+bool launch_op(int cls, const BatchGrids &g, const BatchSlot *slots, const BatchSched &sc, int bin,
+               hipStream_t s) {
+  constexpr int N = N1 - 1;
+  if (op_uses_mfma(cls, N) != MFMA) return false;
+  const dim3 grid(g.op[cls][N][EPB]), threads(OpCfg<N1, EPB, MFMA>::THREADS);
+  if constexpr (op_uses_mfma(0, N) == MFMA)
+    if (cls == 0) hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 0, MFMA>), grid, threads, 0, s, slots, sc, bin);
+  if constexpr (op_uses_mfma(1, N) == MFMA)
+    if (cls == 1) hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 1, MFMA>), grid, threads, 0, s, slots, sc, bin);
+  if constexpr (op_uses_mfma(2, N) == MFMA)
+    if (cls == 2) hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 2, MFMA>), grid, threads, 0, s, slots, sc, bin);
+  if constexpr (op_uses_mfma(3, N) == MFMA)
+    if (cls == 3) hipLaunchKernelGGL((batch_op_kernel<N1, EPB, 3, MFMA>), grid, threads, 0, s, slots, sc, bin);
+  return true;
 }
 
 }  // namespace
 
-int batch_default_epb(int N) {
+int batch_default_epb(int cls, int N) {
   const int n1 = N + 1;
+  if (op_uses_mfma(cls, N)) {
+    const int nt = (n1 * n1 + 15) / 16;
+    return nt >= 8 ? 1 : 8 / nt;
+  }
   return n1 * n1 >= 128 ? 1 : 128 / (n1 * n1);
 }
 
-bool batch_epb_supported(int N, int epb) {
-#define SCASE(n_, epb_) \
-  if (N == n_ && epb == epb_) return true;
-  SEM_BATCH_TILES(SCASE)
-#undef SCASE
+bool batch_epb_supported(int cls, int N, int epb) {
+  if (cls < 0 || cls >= kBatchClasses) return false;
+  const bool mfma = op_uses_mfma(cls, N);
+#define SCASE_V(n_, epb_) \
+  if (!mfma && N == n_ && epb == epb_) return true;
+#define SCASE_M(n_, epb_) \
+  if (mfma && N == n_ && epb == epb_) return true;
+  SEM_BATCH_TILES_VALU(SCASE_V)
+  SEM_BATCH_TILES_MFMA(SCASE_M)
+#undef SCASE_V
+#undef SCASE_M
   return false;
 }
 
@@ -439,15 +504,12 @@ hipError_t batch_prepare() {
   if (e != hipSuccess) return e;
   BatchGrids g;
   std::memset(&g, 0, sizeof(g));
-#define GCASE(n_, epb_)                                                                        \
-  g.op[0][n_][tile_index(n_, epb_)] =                                                          \
-      resident_blocks(batch_op_kernel<n_ + 1, epb_, 0>, OpCfg<n_ + 1, epb_>::THREADS, cus);    \
-  g.op[1][n_][tile_index(n_, epb_)] =                                                          \
-      resident_blocks(batch_op_kernel<n_ + 1, epb_, 1>, OpCfg<n_ + 1, epb_>::THREADS, cus);    \
-  g.op[2][n_][tile_index(n_, epb_)] =                                                          \
-      resident_blocks(batch_op_kernel<n_ + 1, epb_, 2>, OpCfg<n_ + 1, epb_>::THREADS, cus);
-  SEM_BATCH_TILES(GCASE)
-#undef GCASE
+#define GCASE_V(n_, epb_) fill_grid<n_ + 1, epb_, false>(g, cus);
+#define GCASE_M(n_, epb_) fill_grid<n_ + 1, epb_, true>(g, cus);
+  SEM_BATCH_TILES_VALU(GCASE_V)
+  SEM_BATCH_TILES_MFMA(GCASE_M)
+#undef GCASE_V
+#undef GCASE_M
   g.vec[0] = xcd_grid(resident_blocks(batch_vec_kernel<true>, kVecThreads, cus));
   g.vec[1] = xcd_grid(resident_blocks(batch_vec_kernel<false>, kVecThreads, cus));
   (void)hipGetLastError();
@@ -466,15 +528,18 @@ hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSc
     for (int N = 1; N <= kBatchOrders; ++N) {
       const int bin = batch_bin(cls, N);
       if (!((bins >> bin) & 1u)) continue;
-      const int epb = tiles.epb[N];
+      const int epb = tiles.epb[cls][N];
       bool launched = false;
-#define LCASE(n_, epb_)                                                 \
-  if (!launched && N == n_ && epb == epb_) {                            \
-    (void)launch_op<n_ + 1, epb_>(cls, *g, slots, sched, bin, s);       \
-    launched = true;                                                    \
-  }
-      SEM_BATCH_TILES(LCASE)
-#undef LCASE
+#define LCASE_V(n_, epb_)                                                         \
+  if (!launched && N == n_ && epb == epb_)                                        \
+    launched = launch_op<n_ + 1, epb_, false>(cls, *g, slots, sched, bin, s);
+#define LCASE_M(n_, epb_)                                                         \
+  if (!launched && N == n_ && epb == epb_)                                        \
+    launched = launch_op<n_ + 1, epb_, true>(cls, *g, slots, sched, bin, s);
+      SEM_BATCH_TILES_VALU(LCASE_V)
+      SEM_BATCH_TILES_MFMA(LCASE_M)
+#undef LCASE_V
+#undef LCASE_M
       if (!launched) return hipErrorInvalidValue;
     }
   hipLaunchKernelGGL(batch_alpha_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);

@@ -35,7 +35,7 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
     const int64_t idx = base + (int64_t)u * kVecThreads;
     if (idx < L) {
       const Node<N1> n = node_at<N1>(b, idx);
-      const double c = 1.0 / (double)n.mult;
+      const double c = n.inv_mult();
       const double rv = n.boundary ? 0.0 : bvec[idx];
       x[idx] = 0.0;
       r[idx] = rv;
@@ -68,7 +68,7 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t L, int64_t tile,
         const TV rt = (TV)((double)ld_once(r + idx) - alpha * wa);
         r[idx] = rt;
         const double rv = (double)rt;
-        const double c = 1.0 / (double)n.mult;
+        const double c = n.inv_mult();
         rr += c * rv * rv;
         rz += c * rv * ((double)ld_once(minv + idx) * rv);
       }
@@ -99,7 +99,7 @@ __device__ inline TileSums inner_start_tile(const Box &b, int64_t L, int64_t til
       rin[idx] = rv;
       e[idx] = 0.0f;
       p[idx] = 0.0f;
-      const double c = 1.0 / (double)n.mult;
+      const double c = n.inv_mult();
       rz += c * (double)rv * ((double)minv32[idx] * (double)rv);
       rr += c * (double)rv * (double)rv;
     }
@@ -127,7 +127,7 @@ __device__ inline double residual_tile(const Box &b, int64_t L, int64_t tile,
       double rv = 0.0;
       if (!n.boundary) rv = bvec[idx] - gather_copies<N1>(wl, b, n, idx);
       r[idx] = rv;
-      rr += rv * rv / (double)n.mult;
+      rr += rv * rv * n.inv_mult();
     }
   }
   return block_sum<kVecThreads>(rr, sred);

@@ -161,6 +161,10 @@ struct Node {
   int ex, ey, ez;
   bool boundary;  // on a face of the box (homogeneous Dirichlet)
   int mult;       // number of element-local copies (1, 2, 4 or 8)
+  // 1 / mult, exactly (a power of two: no division)
+  __device__ double inv_mult() const {
+    return mult == 1 ? 1.0 : (mult == 2 ? 0.5 : (mult == 4 ? 0.25 : 0.125));
+  }
 };
 
 // All index arithmetic is 32-bit: the element index is below 2^31 and the
@@ -169,8 +173,9 @@ template <int N1>
 __device__ inline Node<N1> node_at(const Box &b, int64_t idx) {
   constexpr int N = N1 - 1;
   constexpr uint32_t NP = N1 * N1 * N1;
-  const uint32_t e = (uint32_t)(idx / NP);
-  const uint32_t loc = (uint32_t)(idx - (int64_t)e * NP);
+  // L < 2^32 (sem_setup refuses larger meshes): 32-bit division by a constant
+  const uint32_t e = (uint32_t)idx / NP;
+  const uint32_t loc = (uint32_t)idx - e * NP;
   Node<N1> n;
   n.i = (int)(loc % N1);
   n.j = (int)((loc / N1) % N1);

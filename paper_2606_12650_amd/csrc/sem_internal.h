@@ -86,6 +86,18 @@ inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) 
 // Jacobi inverse 1/sum with boundary nodes zeroed (inverse).
 enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse = 2 };
 
+// ---------------------------------------------------------------- operator
+// Which element tile an operator runs by default, per arithmetic class (0 and
+// 3 FP64, 1 FP32, 2 BF16) and order N: the matrix-core tile (sem_ax_mfma.h)
+// where it measured faster on MI355X than the vector-unit tiles
+// (sem_ax_tile.h), i.e. from N = 7 in FP64 and from N = 11 in FP32 / BF16.
+__host__ __device__ constexpr bool op_uses_mfma(int cls, int N) {
+  return (cls == 0 || cls == 3) ? N >= 7 : N >= 11;
+}
+
+// Operator implementation request: the default above, or forced.
+enum OpImpl : int { kImplDefault = 0, kImplMfma = 1, kImplValu = 2 };
+
 // ---------------------------------------------------------------- batches
 // Phase of a solve inside a batch (advanced on the device).
 enum SlotPhase : int {
@@ -129,13 +141,13 @@ struct BatchStatus {
   double rnorm2, bnorm2;
 };
 
-// Operator work of a batched iteration is binned by arithmetic class and
-// order: class 0 is FP64 (CG iterations of FP64 solves, true-residual
-// operators of mixed solves), classes 1 and 2 the FP32 and BF16 inner
-// iterations.  Bin kBatchBins holds the streaming tiles of every unfinished
-// solve.
+// Operator work of a batched iteration is binned by class and order: class 0
+// is the FP64 CG iterations of FP64 solves, classes 1 and 2 the FP32 and BF16
+// inner iterations of mixed solves, class 3 the FP64 true-residual operator
+// of their outer steps.  Bin kBatchBins holds the streaming tiles of every
+// unfinished solve.
 constexpr int kBatchOrders = 11;  // batches take orders 1..11
-constexpr int kBatchClasses = 3;
+constexpr int kBatchClasses = 4;
 constexpr int kBatchBins = kBatchClasses * kBatchOrders;
 constexpr int kBatchMaxSlots = 4096;
 __host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }
@@ -151,15 +163,16 @@ struct BatchSched {
   int max_slots;
 };
 
-// Elements per operator item, by order (index 1..11).
+// Elements per operator item, by class and order (index 1..11).
 struct BatchTiles {
-  int epb[kBatchOrders + 1];
+  int epb[kBatchClasses][kBatchOrders + 1];
 };
 
-// Operator tiles compiled for batches: the single-solve kernel's elements per
-// work-group for each order, and twice that where it fits.
-int batch_default_epb(int N);
-bool batch_epb_supported(int N, int epb);
+// Operator tiles compiled for batches, per class and order: elements per
+// work-group of the default tile of that class and order (its single-solve
+// size first).
+int batch_default_epb(int cls, int N);
+bool batch_epb_supported(int cls, int N, int epb);
 // Resident work-groups of every batched kernel on the current device
 // (queried once per process; call before graph capture).
 hipError_t batch_prepare();
@@ -183,15 +196,16 @@ hipError_t launch_fill_c(const Box &b, double *c, hipStream_t s);
 // w = A_L u.  With cg != null (a CG iteration) a prologue first finishes the
 // previous iteration, x += alpha p, then forms p <- Minv r + beta p (u is p,
 // updated in place), and the per-element sums of p.w go to part (E of them).
-hipError_t launch_ax_f64(const Box &b, const double *D, const double *G, double *u, double *w,
-                         const double *r, const double *minv, double *x, CgState *cg,
+// impl: an OpImpl.
+hipError_t launch_ax_f64(const Box &b, int impl, const double *D, const double *G, double *u,
+                         double *w, const double *r, const double *minv, double *x, CgState *cg,
                          double *part, hipStream_t s);
 
 // Low-precision operator (prec SEM_F32 or SEM_BF16): FP32 vectors, G stored
 // as float or bfloat16 bits, D as float (bfloat16-rounded in BF16 mode),
 // FP32 accumulation; the CG variant mirrors launch_ax_f64 (x is the inner
-// correction e).  mfma != 0: the D contractions on the matrix cores.
-hipError_t launch_ax_lowp(const Box &b, int prec, int mfma, const float *D, const void *G, float *u,
+// correction e).  impl: an OpImpl.
+hipError_t launch_ax_lowp(const Box &b, int prec, int impl, const float *D, const void *G, float *u,
                           float *w, const float *r, const float *minv, float *x, CgState *cg,
                           double *part, hipStream_t s);
 // dst[i] = src[i] rounded to float (SEM_F32) or to bfloat16 bits (SEM_BF16).

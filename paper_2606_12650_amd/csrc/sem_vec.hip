@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(kVecThreads)
 #pragma unroll
   for (int u = 0; u < kVecItems; ++u) {
     const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < L) c[idx] = 1.0 / (double)node_at<N1>(b, idx).mult;
+    if (idx < L) c[idx] = node_at<N1>(b, idx).inv_mult();
   }
 }
 

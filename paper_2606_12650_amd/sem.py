@@ -44,12 +44,18 @@ class CgResult:
     rel_res: float
 
 
-def mesh_desc(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=False) -> L.SemMeshDesc:
+def _flags(mfma) -> int:
+    """None: the default kernel per order; True / False: force the matrix-core
+    or the vector-ALU element kernel."""
+    return 0 if mfma is None else (L.SEM_FLAG_MFMA if mfma else L.SEM_FLAG_VALU)
+
+
+def mesh_desc(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=None) -> L.SemMeshDesc:
     return L.SemMeshDesc(int(nelx), int(nely), int(nelz), int(order), float(deform_amp),
-                         _PREC[lowprec], L.SEM_FLAG_MFMA if mfma else 0)
+                         _PREC[lowprec], _flags(mfma))
 
 
-def workspace_bytes(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=False) -> int:
+def workspace_bytes(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=None) -> int:
     d = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec, mfma)
     return int(L.lib().sem_workspace_bytes(ctypes.byref(d)))
 
@@ -57,7 +63,7 @@ def workspace_bytes(nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, mfma=
 class SemOperator:
     """The Poisson operator of one box mesh, set up on the GPU (``sem_setup``)."""
 
-    def __init__(self, nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, device="cuda", mfma=False):
+    def __init__(self, nelx, nely, nelz, order, deform_amp=0.0, lowprec=None, device="cuda", mfma=None):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("SemOperator needs a CUDA (HIP) device")

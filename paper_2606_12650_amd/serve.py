@@ -171,8 +171,9 @@ class GpuExecutor:
         self.iters = int(iters_per_step)
         self.rtol = rtol
         self.batch = SemBatch(max_slots, device=self.device)
-        for order, epb in (tiles or {}).items():
-            self.batch.set_tile(int(order), int(epb))
+        for prec, per_order in (tiles or {}).items():  # {"f64" / "f32" / "bf16": {order: epb}}
+            for order, epb in per_order.items():
+                self.batch.set_tile(int(order), int(epb), prec)
         self.slots: dict = {}
         self.keep = keep_solutions
         self.solutions: dict = {}  # request index -> x (when keep_solutions)

@@ -68,7 +68,7 @@ def test_fp64_batched_equals_alone_all_orders():
     assert torch.equal(x, alone[0][0])
 
 
-@pytest.mark.parametrize("order,tile", [(3, 16), (5, 6), (7, 4), (9, 2)])
+@pytest.mark.parametrize("order,tile", [(3, 16), (5, 6), (7, 4), (8, 2)])
 def test_tile_shape_does_not_change_bits(order, tile):
     A, b = _instance(7, 3, 2, 2, order)
     x0, r0 = A.cg(b, rtol=1e-8)

@@ -72,12 +72,16 @@ def test_setup_fields_match_oracle(N):
 
 # ------------------------------------------------------------------ A.u (a2-a5)
 
+MFMA = pytest.mark.parametrize("mfma", [False, True], ids=["valu", "mfma"])
+
+
+@MFMA
 @pytest.mark.parametrize("N", list(range(1, 13)))
 @pytest.mark.parametrize("amp", [0.0, 0.05])
-def test_ax_all_orders(N, amp):
+def test_ax_all_orders(N, amp, mfma):
     nx, ny, nz = 3, 2, 2
     pr = op.Problem(nx, ny, nz, N, amp)
-    A = sem.SemOperator(nx, ny, nz, N, amp, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, amp, device=DEV, mfma=mfma)
     u_disc = workload.iid_lvector(100 + N, pr.L)
     u_cont = workload.continuous_rhs(200 + N, nx, ny, nz, N, zero_boundary=False)
     w = _cpu(A.ax(_gpu(u_disc), sem.LOCAL)).reshape(pr.mask.shape)
@@ -93,12 +97,13 @@ def test_ax_all_orders(N, amp):
 @pytest.mark.parametrize("mesh,N", [((1, 1, 1), 1), ((1, 1, 1), 7), ((1, 1, 1), 12),
                                     ((5, 1, 1), 3), ((1, 7, 1), 5), ((3, 3, 5), 7),
                                     ((2, 3, 4), 11), ((7, 5, 3), 2)])
-def test_ax_ragged_and_degenerate_meshes(mesh, N):
+@MFMA
+def test_ax_ragged_and_degenerate_meshes(mesh, N, mfma):
     """Element counts that leave the last work-group partly empty, single
     elements (every node on the boundary) and slab meshes."""
     nx, ny, nz = mesh
     pr = op.Problem(nx, ny, nz, N, 0.05)
-    A = sem.SemOperator(nx, ny, nz, N, 0.05, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, 0.05, device=DEV, mfma=mfma)
     u = workload.iid_lvector(7, pr.L)
     for mode, ref in ((sem.LOCAL, pr.ax_local(u)), (sem.ASSEMBLED, pr.ax_assembled(u)),
                       (sem.MASKED, pr.ax(u))):
@@ -124,13 +129,14 @@ def test_ax_config1_and_repeatability():
     assert np.max(np.abs(wl)) <= 1e-12 * np.max(np.abs(pr.ax_local(u)))
 
 
-def test_ax_full_size_sampled():
+@MFMA
+def test_ax_full_size_sampled(mfma):
     """The 32x32x32 deformed N=7 mesh (16.8 M L-entries) in the launch shape
     the bench times; the oracle evaluates sampled elements from their
     neighbourhoods."""
     nx = ny = nz = 32
     N, amp = 7, 0.05
-    A = sem.SemOperator(nx, ny, nz, N, amp, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, amp, device=DEV, mfma=mfma)
     u = workload.continuous_rhs(4, nx, ny, nz, N)
     ug = _gpu(u)
     n3 = (N + 1) ** 3
@@ -183,14 +189,15 @@ def _c_norm(v, c):
     return math.sqrt(float(np.sum(c.reshape(-1) * v.reshape(-1) ** 2)))
 
 
-def test_cg_fixed_iterations_config1():
+@MFMA
+def test_cg_fixed_iterations_config1(mfma):
     """4x4x4 affine, N=7, 50 Jacobi-PCG iterations from x = 0."""
     nx = ny = nz = 4
     N = 7
     pr = op.Problem(nx, ny, nz, N, 0.0)
     b = workload.continuous_rhs(2, nx, ny, nz, N)
     xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, fixed_iter=50)
-    A = sem.SemOperator(nx, ny, nz, N, 0.0, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, 0.0, device=DEV, mfma=mfma)
     xg, res = A.cg(_gpu(b), fixed_iter=50)
     assert res.iters == 50 and res.status == 0
     x = _cpu(xg)
@@ -212,13 +219,15 @@ def test_cg_fixed_iterations_config1():
     assert torch.equal(xg, x3) and res3.rel_res == res.rel_res
 
 
-@pytest.mark.parametrize("mesh,N,every", [((5, 4, 3), 7, 25), ((3, 3, 3), 5, 7), ((4, 3, 2), 9, 1)])
-def test_cg_tolerance_mode(mesh, N, every):
+@pytest.mark.parametrize("mesh,N,every", [((5, 4, 3), 7, 25), ((3, 3, 3), 5, 7), ((4, 3, 2), 9, 1),
+                                          ((2, 3, 2), 11, 10)])
+@MFMA
+def test_cg_tolerance_mode(mesh, N, every, mfma):
     nx, ny, nz = mesh
     pr = op.Problem(nx, ny, nz, N, 0.05)
     b = workload.continuous_rhs(4, nx, ny, nz, N)
     xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, rtol=1e-8)
-    A = sem.SemOperator(nx, ny, nz, N, 0.05, device=DEV)
+    A = sem.SemOperator(nx, ny, nz, N, 0.05, device=DEV, mfma=mfma)
     xg, res = A.cg(_gpu(b), rtol=1e-8, check_every=every)
     assert res.status == 0 and res.rel_res <= 1e-8
     assert abs(res.iters - info["iters"]) <= 2

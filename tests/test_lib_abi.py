@@ -39,14 +39,16 @@ def test_workspace_bytes_host_only():
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
     bad = L.SemMeshDesc(1, 1, 1, 13, 0.0, 0, 0)
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
-    # the matrix-core flag needs a low-precision copy; unknown flag bits are refused
-    bad = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F64, L.SEM_FLAG_MFMA)
-    assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
-    bad = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F32, 2)
-    assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
+    # unknown flag bits are refused; the matrix-core flag costs no memory
+    for flags in (3, 4, -1):
+        bad = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F32, flags)
+        assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
     ok = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_BF16, L.SEM_FLAG_MFMA)
     plain = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_BF16, 0)
     assert lib.sem_workspace_bytes(ctypes.byref(ok)) == lib.sem_workspace_bytes(ctypes.byref(plain)) > 0
+    f64 = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F64, L.SEM_FLAG_MFMA)
+    assert lib.sem_workspace_bytes(ctypes.byref(f64)) == lib.sem_workspace_bytes(
+        ctypes.byref(L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F64, 0)))
 
 
 def test_argument_errors_return_codes_without_launching():
