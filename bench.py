@@ -34,7 +34,7 @@ METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latenc
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_ax_tile.h", "sem_internal.h", "sem_device.h"):
+    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h"):
         with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -453,7 +453,8 @@ def main(argv=None) -> int:
         "ax_frac_of_measured_copy": achieved / copy_gbs,
         "ax_masked_gdofs": gdof / axm_s / 1e9,
         "roofline": {
-            "kernel": "ax_kernel<8, PrecF64, false> (sem_ax element operator, N=7)",
+            "kernel": "ax_mfma_kernel<8, PrecF64, false> (sem_ax element operator, N=7: the "
+                      "matrix-core tile, the library default at this order)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

@@ -199,13 +199,19 @@ __device__ inline Node<N1> node_at(const Box &b, int64_t idx) {
 // copies of the node in w, added in ascending element-local index order.
 // Along each direction a node has one copy, or two when it sits on a face
 // shared with the neighbouring element; the second copy is a fixed address
-// step away (next element, local index N -> 0).  All eight candidate loads
-// are issued together (predicated), so their latencies overlap; a missing
-// copy adds +0.0, which leaves the sum unchanged.  Every copy of a node
-// computes the same sum in the same order: the result is exactly continuous.
-template <int N1, typename T>
-__device__ inline double gather_copies(const T *__restrict__ w, const Box &b, const Node<N1> &n,
-                                       int64_t idx) {
+// step away (next element, local index N -> 0).  A missing copy adds +0.0,
+// which leaves the sum unchanged.  load_copies issues all eight candidate
+// loads unconditionally (a missing copy reads the node itself), so no branch
+// separates them.  Every copy of a node computes the same sum in the same
+// order: the result is exactly continuous.
+template <int N1>
+struct Copies {
+  int64_t addr[8];
+  bool valid[8];
+};
+
+template <int N1>
+__device__ inline Copies<N1> copies_of(const Box &b, const Node<N1> &n, int64_t idx) {
   constexpr int N = N1 - 1;
   constexpr int64_t NP = (int64_t)N1 * N1 * N1;
   const int64_t dx = NP - N;
@@ -215,13 +221,40 @@ __device__ inline double gather_copies(const T *__restrict__ w, const Box &b, co
   const bool sy = n.j == 0 && n.ey > 0, hy = sy || (n.j == N && n.ey < b.ny - 1);
   const bool sz = n.k == 0 && n.ez > 0, hz = sz || (n.k == N && n.ez < b.nz - 1);
   const int64_t lo = idx - (sx ? dx : 0) - (sy ? dy : 0) - (sz ? dz : 0);
-  double v[8];
+  Copies<N1> c;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    const int d = q & 1, c = (q >> 1) & 1, a = q >> 2;
-    const bool valid = (d == 0 || hx) && (c == 0 || hy) && (a == 0 || hz);
-    v[q] = valid ? (double)w[lo + (d ? dx : 0) + (c ? dy : 0) + (a ? dz : 0)] : 0.0;
+    const int d = q & 1, cc = (q >> 1) & 1, a = q >> 2;
+    c.valid[q] = (d == 0 || hx) && (cc == 0 || hy) && (a == 0 || hz);
+    c.addr[q] = c.valid[q] ? lo + (d ? dx : 0) + (cc ? dy : 0) + (a ? dz : 0) : idx;
   }
+  return c;
+}
+
+template <int N1, typename T>
+__device__ inline void load_copies(const T *__restrict__ w, const Copies<N1> &c, T (&v)[8]) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = w[c.addr[q]];
+}
+
+template <int N1, typename T>
+__device__ inline double sum_copies(const Copies<N1> &c, const T (&v)[8]) {
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += c.valid[q] ? (double)v[q] : 0.0;
+  return s;
+}
+
+// The same sum with the loads of missing copies masked off (fewer memory
+// requests for interior nodes; the form the FP64 kernels measured fastest
+// with).
+template <int N1, typename T>
+__device__ inline double gather_copies(const T *__restrict__ w, const Box &b, const Node<N1> &n,
+                                       int64_t idx) {
+  const Copies<N1> c = copies_of<N1>(b, n, idx);
+  double v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = c.valid[q] ? (double)w[c.addr[q]] : 0.0;
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) s += v[q];
