@@ -97,6 +97,53 @@ def _timed(fn):
     return time.perf_counter() - t0, r
 
 
+def bench_precision_order(args, dev, N: int) -> dict:
+    """The precision study at a second order on the same 32x32x32 deformed
+    mesh: FP64 PCG and the inner-outer FP32 / BF16 solves to 1e-8 with the
+    default element kernels, the error of each against the FP64 solution."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    nx = ny = nz = 32
+    amp, rtol = 0.05, 1e-8
+    out = {"N": N}
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        b = torch.from_numpy(workload.continuous_rhs(4, nx, ny, nz, N)).to(dev)
+        x64 = None
+        for prec in (None, "f32", "bf16"):
+            A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=prec, device=dev)
+            x = torch.empty_like(b)
+            mixed = prec is not None
+            A.cg(b, x, rtol=rtol, mixed=mixed)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            steps = 2
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                _, res = A.cg(b, x, rtol=rtol, mixed=mixed)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            entry = {"solves_per_s": 1.0 / wall, "ms_per_solve": wall * 1e3, "iters": res.iters,
+                     "outer_iters": res.outer_iters, "rel_res_fp64": res.rel_res, "status": res.status}
+            if prec is None:
+                x64 = x.clone()
+                c_w = A.export(sem._lib.SEM_FIELD_C)
+                entry["gdofs"] = A.E * N ** 3 * res.iters / wall / 1e9
+                out["fp64"] = entry
+            else:
+                entry["rel_err_vs_fp64_solution"] = math.sqrt(
+                    float((c_w * (x - x64) ** 2).sum()) / float((c_w * x64 ** 2).sum()))
+                entry["speedup_vs_fp64"] = out["fp64"]["ms_per_solve"] / entry["ms_per_solve"]
+                out[prec] = entry
+            print(f"[bench] precision N={N} {prec or 'fp64'}: {entry}", file=sys.stderr, flush=True)
+            A.close()
+            del x
+    torch.cuda.synchronize()
+    return out
+
+
 def bench_batching(args, dev) -> dict:
     """256 independent solves (log-uniform E in [64, 4096], N in {3,5,7,9,11},
     deformed geometry, seeded right-hand sides) to 1e-8: one at a time with
@@ -259,6 +306,7 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batch", action="store_true", help="skip the 256-instance batching study")
     ap.add_argument("--skip-serve", action="store_true", help="skip the serving study")
+    ap.add_argument("--skip-n11", action="store_true", help="skip the precision study at N = 11")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-rates", type=str, default="50,1000")
@@ -411,6 +459,7 @@ def main(argv=None) -> int:
             del Am, xm
         torch.cuda.synchronize()
 
+    precision_n11 = None if args.skip_n11 else bench_precision_order(args, dev, 11)
     batching = None if args.skip_batch else bench_batching(args, dev)
     serving = None if args.skip_serve else bench_serving(args, dev)
 
@@ -466,6 +515,8 @@ def main(argv=None) -> int:
             "kernel_source_hash": khash,
         },
     }
+    if precision_n11 is not None:
+        out["precision_n11"] = precision_n11
     if batching is not None:
         out["batching"] = batching
     if serving is not None:

@@ -610,7 +610,7 @@ BatchLayout batch_layout(int max_slots) {
     at = align_up(at + bytes);
     return off;
   };
-  const size_t bins = semk::kBatchBins + 1;
+  const size_t bins = semk::kBatchLists;
   o.slots = take((size_t)max_slots * sizeof(semk::BatchSlot));
   o.meta = take(bins * 2 * sizeof(int));
   o.slot = take(bins * (size_t)max_slots * sizeof(int));
@@ -628,9 +628,10 @@ uint64_t batch_bins(const sem_batch *B) {
     if (!B->ctx[q]) continue;
     const semk::BatchSlot &S = B->slots[q];
     if (S.mixed)
-      m |= (1ull << semk::batch_bin(3, S.N)) | (1ull << semk::batch_bin(S.mixed == SEM_F32 ? 1 : 2, S.N));
+      m |= (1ull << semk::batch_bin(3, S.N)) | (1ull << semk::batch_bin(S.mixed == SEM_F32 ? 1 : 2, S.N)) |
+           (1ull << (semk::kBatchBins + 1));
     else
-      m |= 1ull << semk::batch_bin(0, S.N);
+      m |= (1ull << semk::batch_bin(0, S.N)) | (1ull << semk::kBatchBins);
   }
   return m;
 }

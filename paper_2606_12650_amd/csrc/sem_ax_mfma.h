@@ -99,8 +99,7 @@ struct MfmaA {
   using TC = typename P::TC;
   TC a[P::kBf16 ? 1 : MfmaTile<N1>::KS];
   mfma_v4s ab;
-  __device__ __forceinline__ void load(const TC *sD, bool transpose) {
-    const int l = threadIdx.x & 63;
+  __device__ __forceinline__ void load(const TC *sD, bool transpose, int l) {
     const int m = l & 15, g = l >> 4;
     if constexpr (P::kBf16) {
 #pragma unroll
@@ -124,10 +123,9 @@ struct MfmaA {
 template <int N1, class P>
 __device__ __forceinline__ typename MfmaOps<P>::Acc mfma_contract(const MfmaA<N1, P> &A,
                                                                  const typename P::TC *in, int d,
-                                                                 int tile) {
+                                                                 int tile, int l) {
   using M = MfmaTile<N1>;
   using TC = typename P::TC;
-  const int l = threadIdx.x & 63;
   const int g = l >> 4;
   const int q = tile * 16 + (l & 15);
   const bool qok = q < M::PL;
@@ -165,8 +163,7 @@ __device__ __forceinline__ typename MfmaOps<P>::Acc mfma_contract(const MfmaA<N1
 // Store the lane's result rows of a column tile to `out` (rows < N1 only).
 template <int N1, class P>
 __device__ __forceinline__ void mfma_store(typename P::TC *out, const typename MfmaOps<P>::Acc &acc,
-                                           int d, int tile) {
-  const int l = threadIdx.x & 63;
+                                           int d, int tile, int l) {
   const int g = l >> 4;
   const int q = tile * 16 + (l & 15);
   if (q >= MfmaTile<N1>::PL) return;
@@ -177,10 +174,10 @@ __device__ __forceinline__ void mfma_store(typename P::TC *out, const typename M
   }
 }
 
-// Same contract as ax_tile<N1, EPB, P, CG> with blockDim = MfmaCfg<N1>::THREADS
+// Same contract as ax_tile<N1, EPB, P, CG, OPQ> with blockDim = MfmaCfg<N1>::THREADS
 // (EPB = MfmaCfg<N1>::EPB).  LDS: sD N1*N1 TC, s1/s2/s3 EPB * AxTile<N1>::TILE
 // TC each, sred blockDim / 64 doubles.
-template <int N1, int EPB, class P, bool CG>
+template <int N1, int EPB, class P, bool CG, bool OPQ = false>
 __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                              const typename P::TG *__restrict__ G, typename P::TV *u,
                                              typename P::TV *__restrict__ w,
@@ -198,7 +195,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   using Acc = typename MfmaOps<P>::Acc;
   constexpr int NP = T::NP;
   constexpr int PL = M::PL;
-  const int tid = threadIdx.x;
+  const int tid = OPQ ? opaque_tid() : (int)threadIdx.x;
   const int wave = tid >> 6;
   const int el = wave / M::NT;
   const int tile = wave - el * M::NT;  // this wave's column tile in every direction
@@ -271,14 +268,14 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
 
   // gradient
   MfmaA<N1, P> A;
-  A.load(sD, false);
+  A.load(sD, false, l);
   Acc ut = {0, 0, 0, 0};
   if (mine) {
-    const Acc ur = mfma_contract<N1, P>(A, U, 0, tile);
-    const Acc us = mfma_contract<N1, P>(A, U, 1, tile);
-    ut = mfma_contract<N1, P>(A, U, 2, tile);
-    mfma_store<N1, P>(R, ur, 0, tile);
-    mfma_store<N1, P>(S, us, 1, tile);
+    const Acc ur = mfma_contract<N1, P>(A, U, 0, tile, l);
+    const Acc us = mfma_contract<N1, P>(A, U, 1, tile, l);
+    ut = mfma_contract<N1, P>(A, U, 2, tile, l);
+    mfma_store<N1, P>(R, ur, 0, tile, l);
+    mfma_store<N1, P>(S, us, 1, tile, l);
   }
   __syncthreads();
 
@@ -299,14 +296,14 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   __syncthreads();
 
   // divergence: r and s in place (own column tile), t in registers
-  A.load(sD, true);
+  A.load(sD, true, l);
   Acc wt = {0, 0, 0, 0};
   if (mine) {
-    const Acc vr = mfma_contract<N1, P>(A, R, 0, tile);
-    const Acc vs = mfma_contract<N1, P>(A, S, 1, tile);
-    wt = mfma_contract<N1, P>(A, U, 2, tile);
-    mfma_store<N1, P>(R, vr, 0, tile);
-    mfma_store<N1, P>(S, vs, 1, tile);
+    const Acc vr = mfma_contract<N1, P>(A, R, 0, tile, l);
+    const Acc vs = mfma_contract<N1, P>(A, S, 1, tile, l);
+    wt = mfma_contract<N1, P>(A, U, 2, tile, l);
+    mfma_store<N1, P>(R, vr, 0, tile, l);
+    mfma_store<N1, P>(S, vs, 1, tile, l);
   }
   __syncthreads();
 

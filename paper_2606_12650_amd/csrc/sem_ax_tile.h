@@ -37,7 +37,7 @@ struct AxTile {
 //   per-element sums of p.(A_L p) go to part_el[e] (summed in a fixed tree).
 // sD: N1*N1, s1/s2 (and s3 when AxTile<N1>::kTiles == 3): EPB *
 // AxTile<N1>::TILE values of TC each, sred: blockDim doubles, all in LDS.
-template <int N1, int EPB, class P, bool CG>
+template <int N1, int EPB, class P, bool CG, bool OPQ = false>
 __device__ __forceinline__ void ax_tile_col(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                         const typename P::TG *__restrict__ G, typename P::TV *u,
                                         typename P::TV *__restrict__ w,
@@ -52,7 +52,7 @@ __device__ __forceinline__ void ax_tile_col(int64_t E, int64_t e0, const typenam
   using TC = typename P::TC;
   constexpr int NP = T::NP;
   constexpr int PL = N1 * N1;
-  const int tid = threadIdx.x;
+  const int tid = OPQ ? opaque_tid() : (int)threadIdx.x;
   const int el = tid / PL;
   const int ij = tid - el * PL;
   const int i = ij % N1;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void ax_tile_col(int64_t E, int64_t e0, const typenam
 // parts to s2 and s3, the t part to s1 once the operand is no longer read),
 // and the transposed contractions read it back.  LDS as ax_tile with three
 // tiles; sred: blockDim doubles.
-template <int N1, int EPB, class P, bool CG>
+template <int N1, int EPB, class P, bool CG, bool OPQ = false>
 __device__ __forceinline__ void ax_tile_split(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                               const typename P::TG *__restrict__ G, typename P::TV *u,
                                               typename P::TV *__restrict__ w,
@@ -229,7 +229,7 @@ __device__ __forceinline__ void ax_tile_split(int64_t E, int64_t e0, const typen
   constexpr int NP = T::NP;
   constexpr int PL = N1 * N1;
   constexpr int KH = (N1 + 1) / 2;  // k values of the first half; the second has N1 - KH
-  const int tid = threadIdx.x;
+  const int tid = OPQ ? opaque_tid() : (int)threadIdx.x;
   const int el = tid / T::TPE;
   const int rr = tid - el * T::TPE;
   const int h = rr / PL;
@@ -361,8 +361,9 @@ __device__ __forceinline__ void ax_tile_split(int64_t E, int64_t e0, const typen
 
 // The element operator on a tile of EPB elements: AxTile<N1>::TPE threads per
 // element (the first EPB * TPE threads of the work-group; any others only
-// join the barriers).  Same contract for both layouts.
-template <int N1, int EPB, class P, bool CG>
+// join the barriers).  Same contract for both layouts.  OPQ: the caller loops
+// over tiles in a persistent kernel (see opaque_tid).
+template <int N1, int EPB, class P, bool CG, bool OPQ = false>
 __device__ __forceinline__ void ax_tile(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                         const typename P::TG *__restrict__ G, typename P::TV *u,
                                         typename P::TV *__restrict__ w,
@@ -373,10 +374,10 @@ __device__ __forceinline__ void ax_tile(int64_t E, int64_t e0, const typename P:
                                         typename P::TC *s1, typename P::TC *s2,
                                         typename P::TC *s3, double *sred) {
   if constexpr (AxTile<N1>::kSplit)
-    ax_tile_split<N1, EPB, P, CG>(E, e0, Dg, G, u, w, r, minv, x, alpha_d, beta_d, part_el, sD, s1,
+    ax_tile_split<N1, EPB, P, CG, OPQ>(E, e0, Dg, G, u, w, r, minv, x, alpha_d, beta_d, part_el, sD, s1,
                                   s2, s3, sred);
   else
-    ax_tile_col<N1, EPB, P, CG>(E, e0, Dg, G, u, w, r, minv, x, alpha_d, beta_d, part_el, sD, s1,
+    ax_tile_col<N1, EPB, P, CG, OPQ>(E, e0, Dg, G, u, w, r, minv, x, alpha_d, beta_d, part_el, sD, s1,
                                 s2, s3, sred);
 }
 

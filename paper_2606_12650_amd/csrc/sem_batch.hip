@@ -142,17 +142,23 @@ __global__ void __launch_bounds__(kSchedThreads)
     s_bin[q] = b;
     const int epb = b < 0 ? 1 : tiles.epb[b / kBatchOrders][S.N];
     s_cnt[q] = b < 0 ? 0 : (int)((S.E + epb - 1) / epb);
-    s_vt[q] = (S.active && S.phase != kPhaseFinished) ? S.vtiles : 0;
+    // streaming list of its family (FP64 or mixed), as a signed count
+    const int vt = (S.active && S.phase != kPhaseFinished) ? S.vtiles : 0;
+    s_vt[q] = S.mixed ? -vt : vt;
   }
   __syncthreads();
   // one wave per bin: ordered compaction by ballot, prefix sums by a wave scan
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int b = wave; b <= kBatchBins; b += kSchedThreads / 64) {
+  for (int b = wave; b < kBatchLists; b += kSchedThreads / 64) {
     int off = 0, run = 0;
     for (int c = 0; c < ms; c += 64) {
       const int q = c + lane;
       int n = 0;
-      if (q < ms) n = b == kBatchBins ? s_vt[q] : (s_bin[q] == b ? s_cnt[q] : 0);
+      if (q < ms) {
+        if (b == kBatchBins) n = max(s_vt[q], 0);
+        else if (b == kBatchBins + 1) n = max(-s_vt[q], 0);
+        else n = s_bin[q] == b ? s_cnt[q] : 0;
+      }
       const bool in = n > 0;
       const unsigned long long m = __ballot(in);
       const int pos = __popcll(m & ((1ull << lane) - 1ull));
@@ -190,10 +196,11 @@ __device__ __forceinline__ void batch_tile(int64_t E, int64_t e0, const typename
                                            typename P::TC *sD, typename P::TC *s1,
                                            typename P::TC *s2, typename P::TC *s3, double *sred) {
   if constexpr (MFMA)
-    ax_tile_mfma<N1, EPB, P, CG>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3,
+    ax_tile_mfma<N1, EPB, P, CG, true>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3,
                                  sred);
   else
-    ax_tile<N1, EPB, P, CG>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3, sred);
+    ax_tile<N1, EPB, P, CG, true>(E, e0, D, G, u, w, r, minv, x, alpha, beta, part, sD, s1, s2, s3,
+                                  sred);
 }
 
 template <int N1, int EPB, int CLS, bool MFMA>
@@ -247,9 +254,9 @@ __global__ void __launch_bounds__((OpCfg<N1, EPB, MFMA>::THREADS))
 
 // ------------------------------------------------------------- streaming
 
-template <int N1>
+template <int N1, bool MIXED>
 __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double *sred) {
-  if (S.mixed == 0) {
+  if constexpr (!MIXED) {
     if (S.phase != kPhaseFp64 || S.st->done != kRunning) return;
     const TileSums t = cg_update_tile<N1, double>(S.box, S.L, tile, S.r, S.w, S.minv,
                                                   S.st->alpha, sred);
@@ -257,17 +264,19 @@ __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double
       S.part_rr[tile] = t.a;
       S.part_rz[tile] = t.b;
     }
-  } else if (S.phase == kPhaseInner) {
-    if (S.st_in->done != kRunning) return;
-    const TileSums t = cg_update_tile<N1, float>(S.box, S.L, tile, S.rin, S.win, S.minv32,
-                                                 S.st_in->alpha, sred);
-    if (threadIdx.x == 0) {
-      S.part_rr[tile] = t.a;
-      S.part_rz[tile] = t.b;
+  } else {
+    if (S.phase == kPhaseInner) {
+      if (S.st_in->done != kRunning) return;
+      const TileSums t = cg_update_tile<N1, float>(S.box, S.L, tile, S.rin, S.win, S.minv32,
+                                                   S.st_in->alpha, sred);
+      if (threadIdx.x == 0) {
+        S.part_rr[tile] = t.a;
+        S.part_rz[tile] = t.b;
+      }
+    } else if (S.phase == kPhaseOuterOp) {
+      const double rr = residual_tile<N1>(S.box, S.L, tile, S.b, S.w, S.r, sred);
+      if (threadIdx.x == 0) S.part_rr[tile] = rr;
     }
-  } else if (S.phase == kPhaseOuterOp) {
-    const double rr = residual_tile<N1>(S.box, S.L, tile, S.b, S.w, S.r, sred);
-    if (threadIdx.x == 0) S.part_rr[tile] = rr;
   }
 }
 
@@ -275,10 +284,10 @@ __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double
 // (e += alpha p, x += ||r|| e) and the inner restart (r_in = r / ||r||,
 // e = p = 0 and the partials of its scalars); these phases are set by the
 // beta launch of the same iteration.
-template <int N1>
+template <int N1, bool MIXED>
 __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double *sred) {
-  if (S.phase == kPhaseFp64Done) {
-    if (S.st->done_stage != 2) return;
+  if constexpr (!MIXED) {
+    if (S.phase != kPhaseFp64Done || S.st->done_stage != 2) return;
     const double alpha = S.st->alpha;
     const int64_t base = (int64_t)tile * kVecTile + threadIdx.x;
 #pragma unroll
@@ -286,30 +295,35 @@ __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double
       const int64_t idx = base + (int64_t)u * kVecThreads;
       if (idx < S.L) S.x[idx] += alpha * S.p[idx];
     }
-  } else if (S.phase == kPhaseInnerDone) {
-    const bool add_p = S.st_in->done_stage == 2;
-    outer_correct_tile(S.L, tile, S.x, S.e, S.pin, (float)S.st_in->alpha, add_p,
-                       sqrt(S.st->rnorm2));
-  } else if (S.phase == kPhaseRestart) {
-    const TileSums t = inner_start_tile<N1>(S.box, S.L, tile, S.r, 1.0 / sqrt(S.st->rnorm2), S.rin,
-                                            S.e, S.pin, S.minv32, sred);
-    if (threadIdx.x == 0) {
-      S.part_rz[tile] = t.a;
-      S.part_rr[tile] = t.b;
+  } else {
+    if (S.phase == kPhaseInnerDone) {
+      const bool add_p = S.st_in->done_stage == 2;
+      outer_correct_tile(S.L, tile, S.x, S.e, S.pin, (float)S.st_in->alpha, add_p,
+                         sqrt(S.st->rnorm2));
+    } else if (S.phase == kPhaseRestart) {
+      const TileSums t = inner_start_tile<N1>(S.box, S.L, tile, S.r, 1.0 / sqrt(S.st->rnorm2),
+                                              S.rin, S.e, S.pin, S.minv32, sred);
+      if (threadIdx.x == 0) {
+        S.part_rz[tile] = t.a;
+        S.part_rr[tile] = t.b;
+      }
     }
   }
 }
 
-template <bool UPDATE>
+// Streaming launches, one per family: FP64 solves (MIXED = false) or mixed
+// solves, so that each compiles only its own paths (registers).
+template <bool UPDATE, bool MIXED>
 __global__ void __launch_bounds__(kVecThreads)
     batch_vec_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
   __shared__ double sred[kVecThreads / 64];
-  const int cnt = sc.meta[2 * kBatchBins], total = sc.meta[2 * kBatchBins + 1];
+  constexpr int list = kBatchBins + (MIXED ? 1 : 0);
+  const int cnt = sc.meta[2 * list], total = sc.meta[2 * list + 1];
   int w0, w1;
   xcd_block_range(total, &w0, &w1);
   if (w0 >= w1) return;
-  const int *pre = sc.prefix + kBatchBins * (sc.max_slots + 1);
-  const int *sl = sc.slot + kBatchBins * sc.max_slots;
+  const int *pre = sc.prefix + list * (sc.max_slots + 1);
+  const int *sl = sc.slot + list * sc.max_slots;
   // the walk is uniform over the work-group: keep it in scalar registers
   int k = __builtin_amdgcn_readfirstlane(find_slot(pre, cnt, w0));
   int first = __builtin_amdgcn_readfirstlane(pre[k]);
@@ -327,9 +341,9 @@ __global__ void __launch_bounds__(kVecThreads)
 #define VCASE(n_)                                \
   case n_:                                       \
     if (UPDATE)                                  \
-      update_item<n_ + 1>(S, tile, sred);        \
+      update_item<n_ + 1, MIXED>(S, tile, sred); \
     else                                         \
-      finish_item<n_ + 1>(S, tile, sred);        \
+      finish_item<n_ + 1, MIXED>(S, tile, sred); \
     break;
       VCASE(1) VCASE(2) VCASE(3) VCASE(4) VCASE(5) VCASE(6)
       VCASE(7) VCASE(8) VCASE(9) VCASE(10) VCASE(11)
@@ -411,7 +425,7 @@ __global__ void __launch_bounds__(kFinThreads)
 // the compiler's resource use allows, times the compute units.
 struct BatchGrids {
   int op[kBatchClasses][kBatchOrders + 1][65];  // [class][order][elements per item]
-  int vec[2];                                   // update, finish
+  int vec[2][2];                                // [update, finish][FP64, mixed]
 };
 std::mutex g_grid_mu;
 std::map<int, BatchGrids> g_grids;
@@ -510,8 +524,10 @@ hipError_t batch_prepare() {
   SEM_BATCH_TILES_MFMA(GCASE_M)
 #undef GCASE_V
 #undef GCASE_M
-  g.vec[0] = xcd_grid(resident_blocks(batch_vec_kernel<true>, kVecThreads, cus));
-  g.vec[1] = xcd_grid(resident_blocks(batch_vec_kernel<false>, kVecThreads, cus));
+  g.vec[0][0] = xcd_grid(resident_blocks(batch_vec_kernel<true, false>, kVecThreads, cus));
+  g.vec[0][1] = xcd_grid(resident_blocks(batch_vec_kernel<true, true>, kVecThreads, cus));
+  g.vec[1][0] = xcd_grid(resident_blocks(batch_vec_kernel<false, false>, kVecThreads, cus));
+  g.vec[1][1] = xcd_grid(resident_blocks(batch_vec_kernel<false, true>, kVecThreads, cus));
   (void)hipGetLastError();
   std::lock_guard<std::mutex> lock(g_grid_mu);
   g_grids[dev] = g;
@@ -543,11 +559,20 @@ hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSc
       if (!launched) return hipErrorInvalidValue;
     }
   hipLaunchKernelGGL(batch_alpha_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
-  hipLaunchKernelGGL((batch_vec_kernel<true>), dim3(g->vec[0]), dim3(kVecThreads), 0, s, slots,
-                     sched);
+  const bool f64 = (bins >> kBatchBins) & 1u, mix = (bins >> (kBatchBins + 1)) & 1u;
+  if (f64)
+    hipLaunchKernelGGL((batch_vec_kernel<true, false>), dim3(g->vec[0][0]), dim3(kVecThreads), 0, s,
+                       slots, sched);
+  if (mix)
+    hipLaunchKernelGGL((batch_vec_kernel<true, true>), dim3(g->vec[0][1]), dim3(kVecThreads), 0, s,
+                       slots, sched);
   hipLaunchKernelGGL(batch_beta_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
-  hipLaunchKernelGGL((batch_vec_kernel<false>), dim3(g->vec[1]), dim3(kVecThreads), 0, s, slots,
-                     sched);
+  if (f64)
+    hipLaunchKernelGGL((batch_vec_kernel<false, false>), dim3(g->vec[1][0]), dim3(kVecThreads), 0, s,
+                       slots, sched);
+  if (mix)
+    hipLaunchKernelGGL((batch_vec_kernel<false, true>), dim3(g->vec[1][1]), dim3(kVecThreads), 0, s,
+                       slots, sched);
   hipLaunchKernelGGL(batch_phase_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots, status);
   return hipGetLastError();
 }

@@ -64,6 +64,17 @@ __device__ __forceinline__ void st_once(T *p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// threadIdx.x through an opaque register move.  A persistent kernel that
+// loops over element tiles calls the tile with this: the compiler then
+// recomputes the tile's thread-index arithmetic in each iteration instead of
+// hoisting it out of the loop into registers held for the whole kernel,
+// which had cost the batched operator kernels a third of their occupancy.
+__device__ __forceinline__ int opaque_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+  return t;
+}
+
 template <class P>
 __device__ inline typename P::TC load_g(const typename P::TG *p) {
   if constexpr (P::kBf16) {

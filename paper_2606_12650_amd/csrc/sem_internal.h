@@ -144,16 +144,17 @@ struct BatchStatus {
 // Operator work of a batched iteration is binned by class and order: class 0
 // is the FP64 CG iterations of FP64 solves, classes 1 and 2 the FP32 and BF16
 // inner iterations of mixed solves, class 3 the FP64 true-residual operator
-// of their outer steps.  Bin kBatchBins holds the streaming tiles of every
-// unfinished solve.
+// of their outer steps.  Bins kBatchBins and kBatchBins + 1 hold the
+// streaming tiles of every unfinished FP64 solve and mixed solve.
 constexpr int kBatchOrders = 11;  // batches take orders 1..11
 constexpr int kBatchClasses = 4;
 constexpr int kBatchBins = kBatchClasses * kBatchOrders;
+constexpr int kBatchLists = kBatchBins + 2;  // operator bins and the two streaming lists
 constexpr int kBatchMaxSlots = 4096;
 __host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }
 
 // Work lists that the schedule kernel rebuilds on the device at the start of
-// every batched iteration (bins 0..kBatchBins, max_slots entries each): the
+// every batched iteration (kBatchLists lists, max_slots entries each): the
 // slots with work in the bin in ascending order, the exclusive prefix sums of
 // their item counts (one more entry: the total), and [count, total].
 struct BatchSched {
@@ -179,7 +180,8 @@ hipError_t batch_prepare();
 
 // One batched iteration over every active slot: the schedule, one operator
 // launch per bin set in `bins` (bit cls * 11 + N - 1), the per-solve scalar
-// launches and the two streaming launches.
+// launches and the streaming launches of the FP64 and mixed solves (bits
+// kBatchBins and kBatchBins + 1 of `bins`: which families are present).
 hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSched &sched,
                                   const BatchTiles &tiles, uint64_t bins, BatchStatus *status,
                                   hipStream_t s);
