@@ -142,7 +142,7 @@ typedef struct {
   int32_t check_every; /* iterations per captured graph replay (<=0: 25)        */
   double inner_rtol;   /* mixed: inner relative tolerance (<=0: 1e-3 for SEM_F32,
                           1e-2 for SEM_BF16)                                   */
-  int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 1000) */
+  int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 5000) */
   int32_t reserved;
 } sem_cg_opts;
 

@@ -36,6 +36,10 @@ int hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+// Inner iteration cap per outer step of the mixed solver when the caller
+// gives none.  The inner solve normally stops at its tolerance first; at
+// N = 11 in FP32 that takes about 1050 iterations, so the cap sits well above.
+constexpr int kDefaultInnerMax = 5000;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of every buffer inside the caller's workspace.  The low-
@@ -465,7 +469,7 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
     // so the inner solve runs to a moderate tolerance with a generous cap
     const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol
                                               : (ctx->desc.lowprec == SEM_BF16 ? 1e-2 : 1e-3);
-    const int inner_max = opts->inner_max > 0 ? opts->inner_max : 1000;
+    const int inner_max = opts->inner_max > 0 ? opts->inner_max : kDefaultInnerMax;
     if (every > inner_max) every = inner_max;
     const Box &bx = ctx->box;
     int inner_total = 0;
@@ -748,7 +752,7 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   S.mixed = opts->mixed ? ctx->desc.lowprec : 0;
   S.active = 1;
   S.inner_total = 0;
-  S.inner_max = opts->inner_max > 0 ? opts->inner_max : 1000;
+  S.inner_max = opts->inner_max > 0 ? opts->inner_max : kDefaultInnerMax;
   const double eta = opts->inner_rtol > 0.0 ? opts->inner_rtol
                                             : (ctx->desc.lowprec == SEM_BF16 ? 1e-2 : 1e-3);
   S.eta2 = eta * eta;

@@ -11,18 +11,18 @@
 // ceil((N+1)^2 / 16) waves; wave w of an element takes column tile w of all
 // three directions.
 //
-// The element's nodes are owned in the layout of the t-direction result: lane
-// l of wave w holds the nodes (i, j, k) with i + (N+1) j = 16 w + l % 16 and k
-// one of the four result rows of its lane group.  HBM accesses in that layout
-// are 16 consecutive values per lane group and k-plane.  Per element:
+// HBM loads and stores run in a flat layout (64 consecutive nodes per wave
+// and instruction); the MFMA results go through three LDS tiles.  Per
+// element:
 //   prologue: load the operand (CG: update x and p first) and G into
 //             registers, operand to LDS tile U
-//   gradient: r and s results to LDS tiles R and S, t result in registers
-//   metric:   at the owned nodes (G from registers), the weighted gradient
-//             back to R, S and U (U is no longer read)
-//   divergence: r and s in place in R and S (a wave reads and writes only
-//             its own column tile's pairs), t in registers
-//   result:   w = (R + S) + t part at the owned nodes, stored to HBM.
+//   gradient: r and s results to R and S; the t result to U once every wave
+//             has read the operand
+//   metric:   at the flat-layout nodes (G from registers), the weighted
+//             gradient back to R, S and U
+//   divergence: r, s and t in place in R, S and U (a wave reads and writes
+//             only its own column tile's pairs)
+//   result:   w = (R + S) + U at the flat-layout nodes, stored to HBM.
 //
 // Lane layouts of the three instructions (lane l, g = l / 16):
 //   f64/f32 16x16x4 step s: A[m = l % 16][c = 4 s + g], B[c = 4 s + g][n = l % 16]
@@ -177,6 +177,11 @@ __device__ __forceinline__ void mfma_store(typename P::TC *out, const typename M
 // Same contract as ax_tile<N1, EPB, P, CG, OPQ> with blockDim = MfmaCfg<N1>::THREADS
 // (EPB = MfmaCfg<N1>::EPB).  LDS: sD N1*N1 TC, s1/s2/s3 EPB * AxTile<N1>::TILE
 // TC each, sred blockDim / 64 doubles.
+//
+// HBM traffic runs in the flat layout: the element's 64 NT threads take its
+// nodes in index order (thread t: nodes t, t + 64 NT, ...), so every load and
+// store is a run of 64 consecutive values.  The t-direction results pass
+// through LDS to meet that layout.
 template <int N1, int EPB, class P, bool CG, bool OPQ = false>
 __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                              const typename P::TG *__restrict__ G, typename P::TV *u,
@@ -195,78 +200,73 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   using Acc = typename MfmaOps<P>::Acc;
   constexpr int NP = T::NP;
   constexpr int PL = M::PL;
+  constexpr int NTT = 64 * M::NT;              // threads per element
+  constexpr int PPT = (NP + NTT - 1) / NTT;    // nodes per thread in the flat layout
   const int tid = OPQ ? opaque_tid() : (int)threadIdx.x;
   const int wave = tid >> 6;
   const int el = wave / M::NT;
   const int tile = wave - el * M::NT;  // this wave's column tile in every direction
   const int l = tid & 63;
-  const int g = l >> 4;
-  const int q = tile * 16 + (l & 15);  // owned pair = i + N1 j
+  const int lt = tid - el * NTT;       // thread index within the element
   const int64_t e = e0 + el;
   const bool mine = el < EPB;
-  const bool active = mine && e < E && q < PL;
+  const bool active = mine && e < E;
   const int slot = mine ? el : 0;
   TC *U = s1 + slot * T::TILE;
   TC *R = s2 + slot * T::TILE;
   TC *S = s3 + slot * T::TILE;
-  const int qi = q % N1, qj = q / N1;
 
   for (int t = tid; t < N1 * N1; t += blockDim.x) sD[t] = Dg[t];
 
-  // prologue at the owned nodes (k = result row v of this lane group).  Every
-  // load is issued unconditionally (lanes that own no node read entry 0 and
-  // drop the value) so that all of them are in flight together; only the
-  // stores are predicated.
-  const int64_t base = e * NP + q;
-  TC uk[4], gk[4][6];
-  int64_t idx[4];
-  bool okv[4];
+  // prologue in the flat layout.  Every load is issued unconditionally (lanes
+  // without a node read entry 0 and drop the value) so that all are in flight
+  // together; only the stores are predicated.
+  int off[PPT];
+  bool okv[PPT];
+  int64_t idx[PPT];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int k = mfma_row<P>(g, v);
-    okv[v] = active && k < N1;
-    idx[v] = okv[v] ? base + (int64_t)k * PL : 0;
+  for (int m = 0; m < PPT; ++m) {
+    const int pt = lt + NTT * m;
+    okv[m] = active && pt < NP;
+    idx[m] = okv[m] ? e * NP + pt : 0;
+    const int pc = pt < NP ? pt : 0;
+    off[m] = (pc / PL) * T::PLANE + ((pc % PL) / N1) * T::P + pc % N1;
   }
-  // all loads first (one round trip), then the updates and their stores
-  TV pv[4], xv[4], mv[4], rv[4];
+  TV pv[PPT], xv[PPT], mv[PPT], rv[PPT];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    pv[v] = ld_once(u + idx[v]);
+  for (int m = 0; m < PPT; ++m) {
+    pv[m] = ld_once(u + idx[m]);
     if (CG) {
-      xv[v] = ld_once(x + idx[v]);
-      mv[v] = ld_once(minv + idx[v]);
-      rv[v] = ld_once(r + idx[v]);
+      xv[m] = ld_once(x + idx[m]);
+      mv[m] = ld_once(minv + idx[m]);
+      rv[m] = ld_once(r + idx[m]);
     }
   }
+  TC gk[PPT][6];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t gi = okv[v] ? (e * 6 * NP + (int64_t)(idx[v] - e * NP)) : 0;
+  for (int m = 0; m < PPT; ++m) {
+    const int64_t gi = okv[m] ? e * 6 * NP + (idx[m] - e * NP) : 0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) gk[v][c] = load_g<P>(G + gi + (okv[v] ? (int64_t)c * NP : 0));
+    for (int c = 0; c < 6; ++c) gk[m][c] = load_g<P>(G + gi + (okv[m] ? (int64_t)c * NP : 0));
   }
+  TC uk[PPT];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    TV val = pv[v];
+  for (int m = 0; m < PPT; ++m) {
+    TV val = pv[m];
     if (CG) {
-      const TV xn = xv[v] + (TV)alpha_d * pv[v];
-      val = mv[v] * rv[v] + (TV)beta_d * pv[v];
-      if (okv[v]) {
-        st_once(x + idx[v], xn);
-        st_once(u + idx[v], val);
+      const TV xn = xv[m] + (TV)alpha_d * pv[m];
+      val = mv[m] * rv[m] + (TV)beta_d * pv[m];
+      if (okv[m]) {
+        st_once(x + idx[m], xn);
+        st_once(u + idx[m], val);
       }
     }
-    uk[v] = okv[v] ? (TC)val : (TC)0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) gk[v][c] = okv[v] ? gk[v][c] : (TC)0;
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int k = mfma_row<P>(g, v);
-    if (mine && k < N1 && q < PL) U[k * T::PLANE + qj * T::P + qi] = contraction_input<P>(uk[v]);
+    uk[m] = okv[m] ? (TC)val : (TC)0;
+    if (mine && lt + NTT * m < NP) U[off[m]] = contraction_input<P>(uk[m]);
   }
   __syncthreads();
 
-  // gradient
+  // gradient: r and s to LDS, t kept until the operand tile is free
   MfmaA<N1, P> A;
   A.load(sD, false, l);
   Acc ut = {0, 0, 0, 0};
@@ -277,46 +277,48 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     mfma_store<N1, P>(R, ur, 0, tile, l);
     mfma_store<N1, P>(S, us, 1, tile, l);
   }
+  __syncthreads();  // every wave has read the operand tile
+  if (mine) mfma_store<N1, P>(U, ut, 2, tile, l);
   __syncthreads();
 
-  // metric at the owned nodes; the weighted gradient is the next contraction's input
-  if (mine && q < PL) {
+  // metric at the flat-layout nodes; the weighted gradient is the next
+  // contraction's input
+  if (mine) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = mfma_row<P>(g, v);
-      if (k < N1) {
-        const int o = k * T::PLANE + qj * T::P + qi;
-        const TC ur = R[o], us = S[o], utv = (TC)ut[v];
-        R[o] = contraction_input<P>(gk[v][0] * ur + gk[v][1] * us + gk[v][2] * utv);
-        S[o] = contraction_input<P>(gk[v][1] * ur + gk[v][3] * us + gk[v][4] * utv);
-        U[o] = contraction_input<P>(gk[v][2] * ur + gk[v][4] * us + gk[v][5] * utv);
+    for (int m = 0; m < PPT; ++m) {
+      if (lt + NTT * m < NP) {
+        const int o = off[m];
+        const TC ur = R[o], us = S[o], utv = U[o];
+        R[o] = contraction_input<P>(gk[m][0] * ur + gk[m][1] * us + gk[m][2] * utv);
+        S[o] = contraction_input<P>(gk[m][1] * ur + gk[m][3] * us + gk[m][4] * utv);
+        U[o] = contraction_input<P>(gk[m][2] * ur + gk[m][4] * us + gk[m][5] * utv);
       }
     }
   }
   __syncthreads();
 
-  // divergence: r and s in place (own column tile), t in registers
+  // divergence, in place: each wave reads and writes only its own column
+  // tile's pairs in R (r), S (s) and U (t)
   A.load(sD, true, l);
-  Acc wt = {0, 0, 0, 0};
   if (mine) {
     const Acc vr = mfma_contract<N1, P>(A, R, 0, tile, l);
     const Acc vs = mfma_contract<N1, P>(A, S, 1, tile, l);
-    wt = mfma_contract<N1, P>(A, U, 2, tile, l);
+    const Acc vt = mfma_contract<N1, P>(A, U, 2, tile, l);
     mfma_store<N1, P>(R, vr, 0, tile, l);
     mfma_store<N1, P>(S, vs, 1, tile, l);
+    mfma_store<N1, P>(U, vt, 2, tile, l);
   }
   __syncthreads();
 
   double acc = 0.0;
-  if (mine && q < PL) {
+  if (mine) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int k = mfma_row<P>(g, v);
-      if (k < N1) {
-        const int o = k * T::PLANE + qj * T::P + qi;
-        const TC val = (R[o] + S[o]) + (TC)wt[v];
-        if (active) w[base + (int64_t)k * PL] = (TV)val;
-        acc += (double)uk[v] * (double)val;
+    for (int m = 0; m < PPT; ++m) {
+      if (lt + NTT * m < NP) {
+        const int o = off[m];
+        const TC val = (R[o] + S[o]) + U[o];
+        if (okv[m]) w[idx[m]] = (TV)val;
+        acc += (double)uk[m] * (double)val;
       }
     }
   }
@@ -326,9 +328,9 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     if (l == 0) sred[wave] = acc;
     __syncthreads();
     if (mine && tile == 0 && l == 0 && e < E) {
-      double s = 0.0;
-      for (int t = 0; t < M::NT; ++t) s += sred[el * M::NT + t];
-      part_el[e] = s;
+      double sum = 0.0;
+      for (int t = 0; t < M::NT; ++t) sum += sred[el * M::NT + t];
+      part_el[e] = sum;
     }
   }
   __syncthreads();  // LDS is free for the next tile

@@ -90,9 +90,9 @@ enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse 
 // Which element tile an operator runs by default, per arithmetic class (0 and
 // 3 FP64, 1 FP32, 2 BF16) and order N: the matrix-core tile (sem_ax_mfma.h)
 // where it measured faster on MI355X than the vector-unit tiles
-// (sem_ax_tile.h), i.e. from N = 7 in FP64 and from N = 11 in FP32 / BF16.
+// (sem_ax_tile.h), i.e. from N = 7 in FP64, N = 8 in FP32 and N = 9 in BF16.
 __host__ __device__ constexpr bool op_uses_mfma(int cls, int N) {
-  return (cls == 0 || cls == 3) ? N >= 7 : N >= 11;
+  return (cls == 0 || cls == 3) ? N >= 7 : (cls == 1 ? N >= 8 : N >= 9);
 }
 
 // Operator implementation request: the default above, or forced.
