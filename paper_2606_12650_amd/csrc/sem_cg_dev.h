@@ -84,7 +84,7 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t L, int64_t tile,
     t.b = block_sum<kVecThreads>(rz, sred);
     return t;
   }
-  constexpr int GS = 8;
+  constexpr int GS = 4;
 #pragma unroll
   for (int g0 = 0; g0 < kVecItems; g0 += GS) {
     Copies<N1> cp[GS];
