@@ -92,8 +92,8 @@ Layout layout_of(const sem_mesh_desc *d) {
   o.p = take(L * sizeof(double));
   o.w = take(L * sizeof(double));
   o.part_ax = take((size_t)b.E() * sizeof(double));  // per-element p.Ap
-  o.part_rr = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
-  o.part_rz = take((size_t)semk::vec_grid_blocks(b.L()) * sizeof(double));
+  o.part_rr = take((size_t)semk::stream_partials(b) * sizeof(double));
+  o.part_rz = take((size_t)semk::stream_partials(b) * sizeof(double));
   o.state = take(sizeof(CgState));
   o.Dlo = o.Glo = o.minv32 = o.e = o.rin = o.pin = o.win = o.state_in = 0;
   if (d->lowprec != SEM_F64) {
@@ -191,7 +191,8 @@ struct sem_ctx {
   float *Dlo, *minv32, *e, *rin, *pin, *win;
   void *Glo;
   CgState *st_in;
-  int64_t n_ax_blocks, n_vec_blocks;  // partial counts: elements, streaming tiles
+  int64_t n_ax_blocks, n_vec_blocks, n_upd_blocks;  // partial counts: elements, streaming
+                                                    // tiles, update tiles
   CgState host_state;  // staging for the state upload / status reads
   CgState host_inner;
   int in_batch;  // 1 while the context is a slot of a batch
@@ -214,7 +215,7 @@ int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   SEM_HIP(semk::launch_ax_f64(b, c->desc.flags, c->D, c->G, c->p, c->w, c->r, c->minv, x, c->st, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
-  SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_vec_blocks, s));
+  SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_upd_blocks, s));
   return SEM_OK;
 }
 
@@ -226,7 +227,7 @@ int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
                                c->pin, c->win, c->rin, c->minv32, c->e, c->st_in, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
-  SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_vec_blocks, s));
+  SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_upd_blocks, s));
   return SEM_OK;
 }
 
@@ -342,6 +343,7 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->st = (CgState *)(c->ws + lay.state);
   c->n_ax_blocks = c->box.E();
   c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
+  c->n_upd_blocks = semk::upd_num_tiles(c->box);
   c->in_batch = 0;
   for (int slot = 0; slot < 2; ++slot) {
     c->graph[slot] = nullptr;
@@ -758,7 +760,7 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   S.eta2 = eta * eta;
   S.E = bx.E();
   S.L = bx.L();
-  S.ntiles = semk::vec_grid_blocks(S.L);
+  S.utiles = (int)semk::upd_num_tiles(bx);
   S.D = ctx->D;
   S.G = ctx->G;
   S.b = b;

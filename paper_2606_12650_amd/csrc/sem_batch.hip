@@ -38,6 +38,9 @@ namespace {
 
 constexpr int kSchedThreads = 1024;
 
+// Orders a batch takes.
+#define SEM_BATCH_ORDERS(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
+
 // Operator tiles compiled for batches (order, elements per work-group).  An
 // order uses the vector-unit tiles or the matrix-core ones of its class, as
 // its single solves do (op_uses_mfma): the single-solve tile first, then a
@@ -155,9 +158,21 @@ __global__ void __launch_bounds__(kSchedThreads)
       const int q = c + lane;
       int n = 0;
       if (q < ms) {
-        if (b == kBatchBins) n = max(s_vt[q], 0);
-        else if (b == kBatchBins + 1) n = max(-s_vt[q], 0);
-        else n = s_bin[q] == b ? s_cnt[q] : 0;
+        if (b >= kBatchUpdLists) {
+          // update tiles of the slots in the operator bins of this family and order
+          const int fam = (b - kBatchUpdLists) / kBatchOrders;
+          const int N = b - kBatchUpdLists - fam * kBatchOrders + 1;
+          const int sb = s_bin[q];
+          const bool in_fam = fam == 0 ? sb == batch_bin(0, N)
+                                       : (sb == batch_bin(1, N) || sb == batch_bin(2, N));
+          n = in_fam ? slots[q].utiles : 0;
+        } else if (b == kBatchBins) {
+          n = max(s_vt[q], 0);
+        } else if (b == kBatchBins + 1) {
+          n = max(-s_vt[q], 0);
+        } else {
+          n = s_bin[q] == b ? s_cnt[q] : 0;
+        }
       }
       const bool in = n > 0;
       const unsigned long long m = __ballot(in);
@@ -254,30 +269,36 @@ __global__ void __launch_bounds__((OpCfg<N1, EPB, MFMA>::THREADS))
 
 // ------------------------------------------------------------- streaming
 
+// The CG update of one update tile of an FP64 solve (MIXED = false) or of
+// an inner solve's FP32 vectors (MIXED = true).
 template <int N1, bool MIXED>
-__device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double *sred) {
+__device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double *sA,
+                                            double *sred) {
   if constexpr (!MIXED) {
-    if (S.phase != kPhaseFp64 || S.st->done != kRunning) return;
-    const TileSums t = cg_update_tile<N1, double>(S.box, S.L, tile, S.r, S.w, S.minv,
-                                                  S.st->alpha, sred);
+    if (S.phase != kPhaseFp64 || S.st->done != kRunning || tile >= S.utiles) return;
+    const TileSums t = cg_update_tile<N1, double>(S.box, tile, S.r, S.w, S.minv, S.st->alpha,
+                                                  sA, sred, (int)threadIdx.x);
     if (threadIdx.x == 0) {
       S.part_rr[tile] = t.a;
       S.part_rz[tile] = t.b;
     }
   } else {
-    if (S.phase == kPhaseInner) {
-      if (S.st_in->done != kRunning) return;
-      const TileSums t = cg_update_tile<N1, float>(S.box, S.L, tile, S.rin, S.win, S.minv32,
-                                                   S.st_in->alpha, sred);
-      if (threadIdx.x == 0) {
-        S.part_rr[tile] = t.a;
-        S.part_rz[tile] = t.b;
-      }
-    } else if (S.phase == kPhaseOuterOp) {
-      const double rr = residual_tile<N1>(S.box, S.L, tile, S.b, S.w, S.r, sred);
-      if (threadIdx.x == 0) S.part_rr[tile] = rr;
+    if (S.phase != kPhaseInner || S.st_in->done != kRunning || tile >= S.utiles) return;
+    const TileSums t = cg_update_tile<N1, float>(S.box, tile, S.rin, S.win, S.minv32,
+                                                 S.st_in->alpha, sA, sred, (int)threadIdx.x);
+    if (threadIdx.x == 0) {
+      S.part_rr[tile] = t.a;
+      S.part_rz[tile] = t.b;
     }
   }
+}
+
+// The FP64 true residual of a mixed solve's outer step on one streaming tile.
+template <int N1>
+__device__ __forceinline__ void residual_item(const BatchSlot &S, int tile, double *sred) {
+  if (S.phase != kPhaseOuterOp || tile >= S.vtiles) return;
+  const double rr = residual_tile<N1>(S.box, S.L, tile, S.b, S.w, S.r, sred);
+  if (threadIdx.x == 0) S.part_rr[tile] = rr;
 }
 
 // The end of an FP64 solve (x += alpha p), the correction of a mixed solve
@@ -311,13 +332,11 @@ __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double
   }
 }
 
-// Streaming launches, one per family: FP64 solves (MIXED = false) or mixed
-// solves, so that each compiles only its own paths (registers).
-template <bool UPDATE, bool MIXED>
-__global__ void __launch_bounds__(kVecThreads)
-    batch_vec_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
-  __shared__ double sred[kVecThreads / 64];
-  constexpr int list = kBatchBins + (MIXED ? 1 : 0);
+// A persistent walk over the items of one work list: each work-group takes
+// a contiguous range of its XCD's share and calls f(slot, item) per item.
+template <class F>
+__device__ __forceinline__ void walk_list(const BatchSlot *__restrict__ slots, const BatchSched &sc,
+                                          int list, F f) {
   const int cnt = sc.meta[2 * list], total = sc.meta[2 * list + 1];
   int w0, w1;
   xcd_block_range(total, &w0, &w1);
@@ -335,23 +354,58 @@ __global__ void __launch_bounds__(kVecThreads)
       first = next;
       next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
     }
-    const BatchSlot &S = slots[__builtin_amdgcn_readfirstlane(sl[k])];
-    const int tile = w - first;
+    f(slots[__builtin_amdgcn_readfirstlane(sl[k])], w - first);
+  }
+}
+
+// The CG update of one order and family (its own launch: the update tile's
+// registers depend on the order).
+template <int N1, bool MIXED>
+__global__ void __launch_bounds__(kVecThreads)
+    batch_upd_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int list) {
+  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sA[UpdTile<N1>::EPT > 1 ? kUpdLds : 1];
+  walk_list(slots, sc, list, [&](const BatchSlot &S, int tile) {
+    update_item<N1, MIXED>(S, tile, sA, sred);
+  });
+}
+
+// The outer steps' true residuals of the mixed solves (every order).
+__global__ void __launch_bounds__(kVecThreads)
+    batch_resid_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
+  __shared__ double sred[kVecThreads / 64];
+  walk_list(slots, sc, kBatchBins + 1, [&](const BatchSlot &S, int tile) {
     switch (S.N) {
-#define VCASE(n_)                                \
-  case n_:                                       \
-    if (UPDATE)                                  \
-      update_item<n_ + 1, MIXED>(S, tile, sred); \
-    else                                         \
-      finish_item<n_ + 1, MIXED>(S, tile, sred); \
-    break;
-      VCASE(1) VCASE(2) VCASE(3) VCASE(4) VCASE(5) VCASE(6)
-      VCASE(7) VCASE(8) VCASE(9) VCASE(10) VCASE(11)
-#undef VCASE
+#define RCASE(n_) \
+  case n_:        \
+    residual_item<n_ + 1>(S, tile, sred); break;
+      RCASE(1) RCASE(2) RCASE(3) RCASE(4) RCASE(5) RCASE(6)
+      RCASE(7) RCASE(8) RCASE(9) RCASE(10) RCASE(11)
+#undef RCASE
       default:
         break;
     }
-  }
+  });
+}
+
+// The phases that end an iteration, one launch per family: FP64 solves
+// (MIXED = false) or mixed solves, so that each compiles only its own paths.
+template <bool MIXED>
+__global__ void __launch_bounds__(kVecThreads)
+    batch_fin_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
+  __shared__ double sred[kVecThreads / 64];
+  walk_list(slots, sc, kBatchBins + (MIXED ? 1 : 0), [&](const BatchSlot &S, int tile) {
+    switch (S.N) {
+#define FCASE(n_) \
+  case n_:        \
+    finish_item<n_ + 1, MIXED>(S, tile, sred); break;
+      FCASE(1) FCASE(2) FCASE(3) FCASE(4) FCASE(5) FCASE(6)
+      FCASE(7) FCASE(8) FCASE(9) FCASE(10) FCASE(11)
+#undef FCASE
+      default:
+        break;
+    }
+  });
 }
 
 // ------------------------------------------------------------- scalars
@@ -376,10 +430,10 @@ __global__ void __launch_bounds__(kFinThreads)
   const int phase = S.phase;
   if (S.mixed == 0) {
     if (phase != kPhaseFp64) return;
-    cg_beta_step(S.st, S.part_rr, S.part_rz, S.ntiles, sred);
+    cg_beta_step(S.st, S.part_rr, S.part_rz, S.utiles, sred);
     if (threadIdx.x == 0 && S.st->done != kRunning) S.phase = kPhaseFp64Done;
   } else if (phase == kPhaseInner) {
-    cg_beta_step(S.st_in, S.part_rr, S.part_rz, S.ntiles, sred);
+    cg_beta_step(S.st_in, S.part_rr, S.part_rz, S.utiles, sred);
     if (threadIdx.x == 0 && S.st_in->done != kRunning) {
       S.inner_total += S.st_in->iter;
       if (S.st_in->iter == 0) {  // the inner solver made no progress
@@ -390,7 +444,7 @@ __global__ void __launch_bounds__(kFinThreads)
       }
     }
   } else if (phase == kPhaseOuterOp) {
-    outer_finish_step(S.st, S.part_rr, S.ntiles, sred);
+    outer_finish_step(S.st, S.part_rr, S.vtiles, sred);
     if (threadIdx.x == 0) S.phase = S.st->done != kRunning ? kPhaseFinished : kPhaseRestart;
   }
 }
@@ -402,7 +456,7 @@ __global__ void __launch_bounds__(kFinThreads)
   if (!S.active) return;
   const int phase = S.phase;
   if (phase == kPhaseRestart) {
-    inner_init_step(S.st_in, S.part_rz, S.part_rr, S.ntiles, S.eta2, S.inner_max, sred);
+    inner_init_step(S.st_in, S.part_rz, S.part_rr, S.vtiles, S.eta2, S.inner_max, sred);
     if (threadIdx.x == 0) S.phase = S.st_in->done == kRunning ? kPhaseInner : kPhaseInnerDone;
   }
   if (threadIdx.x == 0) {
@@ -425,7 +479,9 @@ __global__ void __launch_bounds__(kFinThreads)
 // the compiler's resource use allows, times the compute units.
 struct BatchGrids {
   int op[kBatchClasses][kBatchOrders + 1][65];  // [class][order][elements per item]
-  int vec[2][2];                                // [update, finish][FP64, mixed]
+  int upd[2][kBatchOrders + 1];                 // [FP64, inner][order]
+  int resid;
+  int fin[2];                                   // [FP64, mixed]
 };
 std::mutex g_grid_mu;
 std::map<int, BatchGrids> g_grids;
@@ -524,10 +580,14 @@ hipError_t batch_prepare() {
   SEM_BATCH_TILES_MFMA(GCASE_M)
 #undef GCASE_V
 #undef GCASE_M
-  g.vec[0][0] = xcd_grid(resident_blocks(batch_vec_kernel<true, false>, kVecThreads, cus));
-  g.vec[0][1] = xcd_grid(resident_blocks(batch_vec_kernel<true, true>, kVecThreads, cus));
-  g.vec[1][0] = xcd_grid(resident_blocks(batch_vec_kernel<false, false>, kVecThreads, cus));
-  g.vec[1][1] = xcd_grid(resident_blocks(batch_vec_kernel<false, true>, kVecThreads, cus));
+#define UCASE(n_)                                                                          \
+  g.upd[0][n_] = xcd_grid(resident_blocks(batch_upd_kernel<n_ + 1, false>, kVecThreads, cus)); \
+  g.upd[1][n_] = xcd_grid(resident_blocks(batch_upd_kernel<n_ + 1, true>, kVecThreads, cus));
+  SEM_BATCH_ORDERS(UCASE)
+#undef UCASE
+  g.resid = xcd_grid(resident_blocks(batch_resid_kernel, kVecThreads, cus));
+  g.fin[0] = xcd_grid(resident_blocks(batch_fin_kernel<false>, kVecThreads, cus));
+  g.fin[1] = xcd_grid(resident_blocks(batch_fin_kernel<true>, kVecThreads, cus));
   (void)hipGetLastError();
   std::lock_guard<std::mutex> lock(g_grid_mu);
   g_grids[dev] = g;
@@ -560,19 +620,25 @@ hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSc
     }
   hipLaunchKernelGGL(batch_alpha_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
   const bool f64 = (bins >> kBatchBins) & 1u, mix = (bins >> (kBatchBins + 1)) & 1u;
-  if (f64)
-    hipLaunchKernelGGL((batch_vec_kernel<true, false>), dim3(g->vec[0][0]), dim3(kVecThreads), 0, s,
-                       slots, sched);
+  auto in_use = [&](int cls, int N) { return ((bins >> batch_bin(cls, N)) & 1u) != 0; };
+#define UCASE(n_)                                                                              \
+  if (in_use(0, n_))                                                                           \
+    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, false>), dim3(g->upd[0][n_]), dim3(kVecThreads), \
+                       0, s, slots, sched, batch_upd_list(0, n_));                             \
+  if (in_use(1, n_) || in_use(2, n_))                                                          \
+    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, true>), dim3(g->upd[1][n_]), dim3(kVecThreads),  \
+                       0, s, slots, sched, batch_upd_list(1, n_));
+  SEM_BATCH_ORDERS(UCASE)
+#undef UCASE
   if (mix)
-    hipLaunchKernelGGL((batch_vec_kernel<true, true>), dim3(g->vec[0][1]), dim3(kVecThreads), 0, s,
-                       slots, sched);
+    hipLaunchKernelGGL(batch_resid_kernel, dim3(g->resid), dim3(kVecThreads), 0, s, slots, sched);
   hipLaunchKernelGGL(batch_beta_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
   if (f64)
-    hipLaunchKernelGGL((batch_vec_kernel<false, false>), dim3(g->vec[1][0]), dim3(kVecThreads), 0, s,
-                       slots, sched);
+    hipLaunchKernelGGL((batch_fin_kernel<false>), dim3(g->fin[0]), dim3(kVecThreads), 0, s, slots,
+                       sched);
   if (mix)
-    hipLaunchKernelGGL((batch_vec_kernel<false, true>), dim3(g->vec[1][1]), dim3(kVecThreads), 0, s,
-                       slots, sched);
+    hipLaunchKernelGGL((batch_fin_kernel<true>), dim3(g->fin[1]), dim3(kVecThreads), 0, s, slots,
+                       sched);
   hipLaunchKernelGGL(batch_phase_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots, status);
   return hipGetLastError();
 }

@@ -51,74 +51,146 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
 }
 
 // CG update with the gather-scatter pulled in: r -= alpha mask o QQ^T w;
-// sums ||r||_c^2 and <r, Minv r>_c (FP64 even for FP32 vectors).  FP64
-// vectors: entry by entry, missing copies masked.  FP32 vectors: all loads of
-// the thread's entries are issued first (clamped, branch-free addresses),
-// then the arithmetic and the predicated stores; this measured 1.7x faster
-// for FP32 and slower for FP64 (register pressure).
+// sums ||r||_c^2 and <r, Minv r>_c (FP64 even for FP32 vectors).
+//
+// The tile is element-aligned (UpdTile): each thread owns KN planes of one
+// (i, j) column of an element, so every load of w, r and Minv is a
+// coalesced run of a plane, and the copies of a node that sit in other
+// elements are reached in pairs along one direction at a time:
+//   P = w(node) + w(y copy)                  pair across a y face,
+//   A = P(this z level) + P(other z level)   pair across a z face,
+//   S = A(this column) + A(x copy column)    pair across an x face.
+// Each pair is one commutative addition of the same two numbers for every
+// copy of the node (a missing copy leaves the other operand alone), so all
+// copies get the same bits.  The A of the x copy column comes from LDS when
+// that column is in the tile and is recomputed from w otherwise.  Missing
+// copies' loads are clamped to the node itself, so the loads carry no branch.
+// tid is threadIdx.x (persistent kernels pass it through opaque_tid).
+template <int N1>
+struct UpdTile {
+  static constexpr int N = N1 - 1;
+  static constexpr int COLS = N1 * N1;
+  static constexpr int NP = COLS * N1;
+  static constexpr int KS = upd_ks(N1);    // threads per column
+  static constexpr int EPT = upd_ept(N1);  // elements per tile
+  static constexpr int KP = upd_kp(N1);    // tiles per element (plane ranges)
+  static constexpr int KT = (N1 + KP - 1) / KP;  // planes per tile
+  static constexpr int KN = (KT + KS - 1) / KS;  // planes per thread
+  static constexpr int THREADS = EPT * KS * COLS;
+  static_assert(THREADS <= kVecThreads, "update tile larger than its work-group");
+  static_assert(EPT == 1 || (KS == 1 && KP == 1 && EPT * NP <= kUpdLds),
+                "multi-element update tiles keep whole elements in LDS");
+};
+
+// The A values (y and z pairs) of planes kb .. kb + KN - 1 of the column at
+// w + col0 (the address of its plane 0).
+template <int N1, int KN, typename TV>
+__device__ __forceinline__ void upd_column(const TV *__restrict__ w, int64_t col0, int kb,
+                                           bool hy, int64_t yoff, bool z_lo, bool z_hi,
+                                           int64_t dz, double (&A)[KN]) {
+  constexpr int N = N1 - 1, COLS = N1 * N1;
+  double own[KN], yv[KN];
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) {
+    const int64_t a = col0 + (int64_t)min(kb + kk, N) * COLS;
+    own[kk] = (double)w[a];
+    yv[kk] = (double)w[hy ? a + yoff : a];
+  }
+  const int64_t lo = col0 - dz + (int64_t)N * COLS, hi = col0 + dz;
+  const double zl = (double)w[z_lo ? lo : col0];
+  const double zyl = (double)w[z_lo && hy ? lo + yoff : col0];
+  const double zh = (double)w[z_hi ? hi : col0];
+  const double zyh = (double)w[z_hi && hy ? hi + yoff : col0];
+  const double pl = hy ? zl + zyl : zl, ph = hy ? zh + zyh : zh;
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) {
+    A[kk] = hy ? own[kk] + yv[kk] : own[kk];
+    if (z_lo && kb + kk == 0) A[kk] = A[kk] + pl;
+    if (z_hi && kb + kk == N) A[kk] = A[kk] + ph;
+  }
+}
+
 template <int N1, typename TV>
-__device__ inline TileSums cg_update_tile(const Box &b, int64_t L, int64_t tile, TV *__restrict__ r,
+__device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__restrict__ r,
                                           const TV *__restrict__ w, const TV *__restrict__ minv,
-                                          double alpha, double *sred) {
+                                          double alpha, double *sA, double *sred,
+                                          int tid) {
+  using U = UpdTile<N1>;
+  constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
+  const bool act = tid < U::THREADS;
+  const int t = act ? tid : 0;
+  const int el = t / (U::KS * COLS), rem = t - el * (U::KS * COLS);
+  const int ks = rem / COLS, col = rem - ks * COLS;
+  const int i = col % N1, j = col / N1;
+  const int64_t grp = tile / U::KP;
+  const int kb = (int)(tile - grp * U::KP) * U::KT + ks * KN;  // first plane of the thread
+  const int64_t E = b.E();
+  const int64_t e_raw = grp * U::EPT + el;
+  const bool live = act && e_raw < E;
+  const uint32_t e = (uint32_t)(e_raw < E ? e_raw : E - 1);
+  const uint32_t eyz = b.fdx.div(e);
+  const int ex = (int)(e - eyz * (uint32_t)b.nx);
+  const uint32_t ezz = b.fdy.div(eyz);
+  const int ey = (int)(eyz - ezz * (uint32_t)b.ny), ez = (int)ezz;
+  const int64_t dy = (int64_t)b.nx * NP, dz = dy * b.ny;
+  const bool hy = (j == 0 && ey > 0) || (j == N && ey < b.ny - 1);
+  const int64_t yoff = j == 0 ? (int64_t)N * N1 - dy : dy - (int64_t)N * N1;
+  const bool z_lo = kb == 0 && ez > 0;
+  const bool z_hi = kb <= N && kb + KN > N && ez < b.nz - 1;
+  const bool hx = (i == 0 && ex > 0) || (i == N && ex < b.nx - 1);
+  const bool x_in = U::EPT > 1 && hx && (i == 0 ? el > 0 : el < U::EPT - 1);
+  const int64_t col0 = (int64_t)e * NP + col;
+  double rv[KN], mv[KN];
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) {
+    const int64_t a = col0 + (int64_t)min(kb + kk, N) * COLS;
+    rv[kk] = (double)ld_once(r + a);
+    mv[kk] = (double)ld_once(minv + a);
+  }
+  double A[KN];
+  upd_column<N1, KN, TV>(w, col0, kb, hy, yoff, z_lo, z_hi, dz, A);
+  double X[KN];
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) X[kk] = 0.0;
+  if (hx && !x_in) {
+    // the x copy column lies in the neighbouring element of another tile
+    const int64_t xc = i == 0 ? col0 - NP + N : col0 + NP - N;
+    upd_column<N1, KN, TV>(w, xc, kb, hy, yoff, z_lo, z_hi, dz, X);
+  }
+  if constexpr (U::EPT > 1) {
+#pragma unroll
+    for (int kk = 0; kk < KN; ++kk) sA[el * NP + kk * COLS + col] = A[kk];
+    __syncthreads();
+    if (x_in) {
+      const int xo = (i == 0 ? el - 1 : el + 1) * NP + j * N1 + (N - i);
+#pragma unroll
+      for (int kk = 0; kk < KN; ++kk) X[kk] = sA[xo + kk * COLS];
+    }
+  }
+  const bool bx = (i == 0 && ex == 0) || (i == N && ex == b.nx - 1);
+  const bool by = (j == 0 && ey == 0) || (j == N && ey == b.ny - 1);
+  const int mxy = (hx ? 2 : 1) * (hy ? 2 : 1);
   double rr = 0.0, rz = 0.0;
-  const int64_t base = tile * kVecTile + threadIdx.x;
-  if constexpr (sizeof(TV) == 8) {
 #pragma unroll
-    for (int u = 0; u < kVecItems; ++u) {
-      const int64_t idx = base + (int64_t)u * kVecThreads;
-      if (idx < L) {
-        const Node<N1> n = node_at<N1>(b, idx);
-        if (!n.boundary) {
-          const double wa = gather_copies<N1>(w, b, n, idx);
-          const TV rt = (TV)((double)ld_once(r + idx) - alpha * wa);
-          r[idx] = rt;
-          const double rv = (double)rt;
-          const double c = n.inv_mult();
-          rr += c * rv * rv;
-          rz += c * rv * ((double)ld_once(minv + idx) * rv);
-        }
-      }
-    }
-    TileSums t;
-    t.a = block_sum<kVecThreads>(rr, sred);
-    t.b = block_sum<kVecThreads>(rz, sred);
-    return t;
-  }
-  constexpr int GS = 4;
-#pragma unroll
-  for (int g0 = 0; g0 < kVecItems; g0 += GS) {
-    Copies<N1> cp[GS];
-    TV wv[GS][8], rv[GS], mv[GS];
-    bool on[GS];
-    double c[GS];
-#pragma unroll
-    for (int u = 0; u < GS; ++u) {
-      const int64_t idx0 = base + (int64_t)(g0 + u) * kVecThreads;
-      const int64_t idx = idx0 < L ? idx0 : L - 1;
-      const Node<N1> n = node_at<N1>(b, idx);
-      on[u] = idx0 < L && !n.boundary;
-      c[u] = n.inv_mult();
-      cp[u] = copies_of<N1>(b, n, idx);
-      load_copies<N1, TV>(w, cp[u], wv[u]);
-      rv[u] = ld_once(r + idx);
-      mv[u] = ld_once(minv + idx);
-    }
-#pragma unroll
-    for (int u = 0; u < GS; ++u) {
-      if (on[u]) {
-        const double wa = sum_copies<N1, TV>(cp[u], wv[u]);
-        const TV rt = (TV)((double)rv[u] - alpha * wa);
-        r[base + (int64_t)(g0 + u) * kVecThreads] = rt;
-        const double rd = (double)rt;
-        rr += c[u] * rd * rd;
-        rz += c[u] * rd * ((double)mv[u] * rd);
-      }
+  for (int kk = 0; kk < KN; ++kk) {
+    const int k = kb + kk;
+    const bool bz = (k == 0 && ez == 0) || (k == N && ez == b.nz - 1);
+    if (live && k <= N && !bx && !by && !bz) {
+      const double S = hx ? A[kk] + X[kk] : A[kk];
+      const TV rt = (TV)(rv[kk] - alpha * S);
+      r[col0 + (int64_t)k * COLS] = rt;
+      const bool hz = (k == 0 && ez > 0) || (k == N && ez < b.nz - 1);
+      const int m = mxy * (hz ? 2 : 1);
+      const double c = m == 1 ? 1.0 : (m == 2 ? 0.5 : (m == 4 ? 0.25 : 0.125));
+      const double rd = (double)rt;
+      rr += c * rd * rd;
+      rz += c * rd * (mv[kk] * rd);
     }
   }
-  TileSums t;
-  t.a = block_sum<kVecThreads>(rr, sred);
-  t.b = block_sum<kVecThreads>(rz, sred);
-  return t;
+  TileSums ts;
+  ts.a = block_sum<kVecThreads>(rr, sred);
+  ts.b = block_sum<kVecThreads>(rz, sred);
+  return ts;
 }
 
 // Inner start of the inner-outer CG: r_in = r / ||r||_c in FP32, e = 0,

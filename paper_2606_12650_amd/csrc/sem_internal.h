@@ -81,6 +81,31 @@ inline int64_t vec_num_blocks(int64_t n) { return (n + kVecTile - 1) / kVecTile;
 // tiles padded to a multiple of the XCD count.
 inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) / 8); }
 
+// Tiles of the CG update (the gather-scatter pulled into r -= alpha w) are
+// element-aligned: upd_ept consecutive elements per tile with upd_ks threads
+// per (i, j) column, or one element in upd_kp plane ranges at the highest
+// orders; a tile fits kVecThreads threads and, with several elements, keeps
+// them in kUpdLds doubles of LDS.
+__host__ __device__ constexpr int upd_ks(int n1) {
+  return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11) ? 2 : 1);
+}
+__host__ __device__ constexpr int upd_ept(int n1) {
+  return upd_ks(n1) * n1 * n1 > kVecThreads / 2 ? 1 : kVecThreads / (upd_ks(n1) * n1 * n1);
+}
+__host__ __device__ constexpr int upd_kp(int n1) { return n1 >= 12 ? 2 : 1; }
+constexpr int kUpdLds = 2048;
+inline int64_t upd_num_tiles(const Box &b) {
+  const int n1 = b.N + 1;
+  return (b.E() + upd_ept(n1) - 1) / upd_ept(n1) * upd_kp(n1);
+}
+// Launch size and partial count of the update (a multiple of the XCD count).
+inline int64_t upd_grid_blocks(const Box &b) { return 8 * ((upd_num_tiles(b) + 7) / 8); }
+// Partials a solve's streaming reductions need room for.
+inline int64_t stream_partials(const Box &b) {
+  const int64_t v = vec_grid_blocks(b.L()), u = upd_grid_blocks(b);
+  return v > u ? v : u;
+}
+
 // What the gather kernel writes at a node: the sum of its copies
 // (assembled), the same with box-boundary nodes zeroed (masked), or the
 // Jacobi inverse 1/sum with boundary nodes zeroed (inverse).
@@ -114,15 +139,15 @@ enum SlotPhase : int {
 struct BatchSlot {
   Box box;
   int N;
-  int vtiles;  // streaming tiles (vec_num_blocks(L))
+  int vtiles;  // streaming tiles (vec_num_blocks(L)); partials of the streaming phases
   int mixed;   // 0: FP64, else the low-precision copy's sem_prec
   int active;
   int phase;  // SlotPhase, written by the device
   int inner_total;
   int inner_max;
-  int pad;
+  int utiles;  // update tiles (upd_num_tiles); partials of the CG update
   double eta2;
-  int64_t E, L, ntiles;  // ntiles: streaming partial count (vec_grid_blocks(L))
+  int64_t E, L;
   const double *D, *G, *b;
   double *minv, *r, *p, *w, *x;
   const float *Dlo;
@@ -144,14 +169,21 @@ struct BatchStatus {
 // Operator work of a batched iteration is binned by class and order: class 0
 // is the FP64 CG iterations of FP64 solves, classes 1 and 2 the FP32 and BF16
 // inner iterations of mixed solves, class 3 the FP64 true-residual operator
-// of their outer steps.  Bins kBatchBins and kBatchBins + 1 hold the
-// streaming tiles of every unfinished FP64 solve and mixed solve.
+// of their outer steps.  Lists kBatchBins and kBatchBins + 1 hold the
+// streaming tiles of every unfinished FP64 solve and mixed solve; after them
+// come the update tiles of the CG update, per order, of the FP64 solves
+// (family 0, the slots of bin (0, N)) and of the inner solves (family 1, bins
+// (1, N) and (2, N)).
 constexpr int kBatchOrders = 11;  // batches take orders 1..11
 constexpr int kBatchClasses = 4;
 constexpr int kBatchBins = kBatchClasses * kBatchOrders;
-constexpr int kBatchLists = kBatchBins + 2;  // operator bins and the two streaming lists
+constexpr int kBatchUpdLists = kBatchBins + 2;
+constexpr int kBatchLists = kBatchUpdLists + 2 * kBatchOrders;
 constexpr int kBatchMaxSlots = 4096;
 __host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }
+__host__ __device__ inline int batch_upd_list(int fam, int N) {
+  return kBatchUpdLists + fam * kBatchOrders + (N - 1);
+}
 
 // Work lists that the schedule kernel rebuilds on the device at the start of
 // every batched iteration (kBatchLists lists, max_slots entries each): the

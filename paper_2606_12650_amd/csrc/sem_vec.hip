@@ -71,16 +71,16 @@ __global__ void __launch_bounds__(kFinThreads)
 
 template <int N1, typename TV>
 __global__ void __launch_bounds__(kVecThreads)
-    cg_update_kernel(Box b, int64_t L, int64_t ntiles, TV *__restrict__ r,
-                     const TV *__restrict__ w, const TV *__restrict__ minv,
-                     CgState *__restrict__ st, double *__restrict__ part_rr,
-                     double *__restrict__ part_rz) {
+    cg_update_kernel(Box b, int64_t ntiles, TV *__restrict__ r, const TV *__restrict__ w,
+                     const TV *__restrict__ minv, CgState *__restrict__ st,
+                     double *__restrict__ part_rr, double *__restrict__ part_rz) {
   __shared__ double sred[kVecThreads / 64];
+  __shared__ double sA[UpdTile<N1>::EPT > 1 ? kUpdLds : 1];
   if (st->done) return;
   const double alpha = st->alpha;
   const int64_t tile = xcd_tile(ntiles);
   TileSums t{0.0, 0.0};
-  if (tile < ntiles) t = cg_update_tile<N1, TV>(b, L, tile, r, w, minv, alpha, sred);
+  if (tile < ntiles) t = cg_update_tile<N1, TV>(b, tile, r, w, minv, alpha, sA, sred, (int)threadIdx.x);
   if (threadIdx.x == 0) {
     part_rr[tile] = t.a;
     part_rz[tile] = t.b;
@@ -336,19 +336,19 @@ hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part
 
 hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  const int64_t L = b.L();
-  const int64_t nt = vec_num_blocks(L);
-  DISPATCH_N_MODE(b, double, cg_update_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt,
-                  r, w, minv, st, part_rr, part_rz);
+  if (b.E() == 0) return hipSuccess;
+  const int64_t nt = upd_num_tiles(b);
+  DISPATCH_N_MODE(b, double, cg_update_kernel, dim3((unsigned)upd_grid_blocks(b)), dim3(kVecThreads),
+                  0, s, b, nt, r, w, minv, st, part_rr, part_rz);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
                                 CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  const int64_t L = b.L();
-  const int64_t nt = vec_num_blocks(L);
-  DISPATCH_N_MODE(b, float, cg_update_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt,
-                  r, w, minv, st, part_rr, part_rz);
+  if (b.E() == 0) return hipSuccess;
+  const int64_t nt = upd_num_tiles(b);
+  DISPATCH_N_MODE(b, float, cg_update_kernel, dim3((unsigned)upd_grid_blocks(b)), dim3(kVecThreads),
+                  0, s, b, nt, r, w, minv, st, part_rr, part_rz);
   return hipGetLastError();
 }
 
