@@ -191,8 +191,8 @@ struct sem_ctx {
   float *Dlo, *minv32, *e, *rin, *pin, *win;
   void *Glo;
   CgState *st_in;
-  int64_t n_ax_blocks, n_vec_blocks, n_upd_blocks;  // partial counts: elements, streaming
-                                                    // tiles, update tiles
+  // partial counts: elements, streaming tiles, FP64 and FP32 update tiles
+  int64_t n_ax_blocks, n_vec_blocks, n_upd_blocks, n_upd_blocks_in;
   CgState host_state;  // staging for the state upload / status reads
   CgState host_inner;
   int in_batch;  // 1 while the context is a slot of a batch
@@ -227,7 +227,7 @@ int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
                                c->pin, c->win, c->rin, c->minv32, c->e, c->st_in, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
   SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
-  SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_upd_blocks, s));
+  SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_upd_blocks_in, s));
   return SEM_OK;
 }
 
@@ -343,7 +343,8 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->st = (CgState *)(c->ws + lay.state);
   c->n_ax_blocks = c->box.E();
   c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
-  c->n_upd_blocks = semk::upd_num_tiles(c->box);
+  c->n_upd_blocks = semk::upd_num_tiles(c->box, true);
+  c->n_upd_blocks_in = semk::upd_num_tiles(c->box, false);
   c->in_batch = 0;
   for (int slot = 0; slot < 2; ++slot) {
     c->graph[slot] = nullptr;
@@ -760,7 +761,7 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   S.eta2 = eta * eta;
   S.E = bx.E();
   S.L = bx.L();
-  S.utiles = (int)semk::upd_num_tiles(bx);
+  S.utiles = (int)semk::upd_num_tiles(bx, S.mixed == 0);
   S.D = ctx->D;
   S.G = ctx->G;
   S.b = b;

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "sem_ax_mfma.h"
 #include "sem_ax_tile.h"
@@ -361,10 +362,13 @@ __device__ __forceinline__ void walk_list(const BatchSlot *__restrict__ slots, c
 // The CG update of one order and family (its own launch: the update tile's
 // registers depend on the order).
 template <int N1, bool MIXED>
-__global__ void __launch_bounds__(kVecThreads)
+using BatchUpd = UpdTile<N1, typename std::conditional<MIXED, float, double>::type>;
+
+template <int N1, bool MIXED>
+__global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
     batch_upd_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int list) {
-  __shared__ double sred[kVecThreads / 64];
-  __shared__ double sA[UpdTile<N1>::EPT > 1 ? kUpdLds : 1];
+  __shared__ double sred[BatchUpd<N1, MIXED>::BLOCK / 64];
+  __shared__ double sA[BatchUpd<N1, MIXED>::LDS];
   walk_list(slots, sc, list, [&](const BatchSlot &S, int tile) {
     update_item<N1, MIXED>(S, tile, sA, sred);
   });
@@ -580,9 +584,11 @@ hipError_t batch_prepare() {
   SEM_BATCH_TILES_MFMA(GCASE_M)
 #undef GCASE_V
 #undef GCASE_M
-#define UCASE(n_)                                                                          \
-  g.upd[0][n_] = xcd_grid(resident_blocks(batch_upd_kernel<n_ + 1, false>, kVecThreads, cus)); \
-  g.upd[1][n_] = xcd_grid(resident_blocks(batch_upd_kernel<n_ + 1, true>, kVecThreads, cus));
+#define UCASE(n_)                                                                     \
+  g.upd[0][n_] = xcd_grid(                                                              \
+      resident_blocks(batch_upd_kernel<n_ + 1, false>, BatchUpd<n_ + 1, false>::BLOCK, cus));  \
+  g.upd[1][n_] = xcd_grid(                                                              \
+      resident_blocks(batch_upd_kernel<n_ + 1, true>, BatchUpd<n_ + 1, true>::BLOCK, cus));
   SEM_BATCH_ORDERS(UCASE)
 #undef UCASE
   g.resid = xcd_grid(resident_blocks(batch_resid_kernel, kVecThreads, cus));
@@ -623,11 +629,13 @@ hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSc
   auto in_use = [&](int cls, int N) { return ((bins >> batch_bin(cls, N)) & 1u) != 0; };
 #define UCASE(n_)                                                                              \
   if (in_use(0, n_))                                                                           \
-    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, false>), dim3(g->upd[0][n_]), dim3(kVecThreads), \
-                       0, s, slots, sched, batch_upd_list(0, n_));                             \
+    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, false>), dim3(g->upd[0][n_]),                 \
+                       dim3(BatchUpd<n_ + 1, false>::BLOCK), 0, s, slots, sched,              \
+                       batch_upd_list(0, n_));                                                 \
   if (in_use(1, n_) || in_use(2, n_))                                                          \
-    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, true>), dim3(g->upd[1][n_]), dim3(kVecThreads),  \
-                       0, s, slots, sched, batch_upd_list(1, n_));
+    hipLaunchKernelGGL((batch_upd_kernel<n_ + 1, true>), dim3(g->upd[1][n_]),                  \
+                       dim3(BatchUpd<n_ + 1, true>::BLOCK), 0, s, slots, sched,               \
+                       batch_upd_list(1, n_));
   SEM_BATCH_ORDERS(UCASE)
 #undef UCASE
   if (mix)

@@ -65,9 +65,12 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
 // copies get the same bits.  The A of the x copy column comes from LDS when
 // that column is in the tile and is recomputed from w otherwise.  Missing
 // copies' loads are clamped to the node itself, so the loads carry no branch.
-// tid is threadIdx.x (persistent kernels pass it through opaque_tid).
-template <int N1>
+// The work-group has BLOCK threads; tid is threadIdx.x.  LINEAR tiles (FP64
+// from order 9) take kVecTile consecutive entries instead, each node summing
+// its copies in ascending element-local order with missing copies masked.
+template <int N1, typename TV>
 struct UpdTile {
+  static constexpr bool LINEAR = upd_linear(N1, sizeof(TV) == 8);
   static constexpr int N = N1 - 1;
   static constexpr int COLS = N1 * N1;
   static constexpr int NP = COLS * N1;
@@ -77,9 +80,11 @@ struct UpdTile {
   static constexpr int KT = (N1 + KP - 1) / KP;  // planes per tile
   static constexpr int KN = (KT + KS - 1) / KS;  // planes per thread
   static constexpr int THREADS = EPT * KS * COLS;
-  static_assert(THREADS <= kVecThreads, "update tile larger than its work-group");
-  static_assert(EPT == 1 || (KS == 1 && KP == 1 && EPT * NP <= kUpdLds),
-                "multi-element update tiles keep whole elements in LDS");
+  static constexpr int BLOCK = LINEAR ? kVecThreads : 64 * ((THREADS + 63) / 64);
+  // LDS: the A values of every plane slot of the tile (EPT > 1 only)
+  static constexpr int LDS = (!LINEAR && EPT > 1) ? EPT * KS * KN * COLS : 1;
+  static_assert(BLOCK <= 512, "update tile larger than its work-group");
+  static_assert(8 * LDS <= 32 * 1024, "update tile LDS above 32 KiB");
 };
 
 // The A values (y and z pairs) of planes kb .. kb + KN - 1 of the column at
@@ -110,12 +115,44 @@ __device__ __forceinline__ void upd_column(const TV *__restrict__ w, int64_t col
   }
 }
 
+template <int N1>
+__device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
+                                                 double *__restrict__ r,
+                                                 const double *__restrict__ w,
+                                                 const double *__restrict__ minv, double alpha,
+                                                 double *sred, int tid) {
+  const int64_t L = b.L();
+  double rr = 0.0, rz = 0.0;
+  const int64_t base = tile * kVecTile + tid;
+#pragma unroll
+  for (int u = 0; u < kVecItems; ++u) {
+    const int64_t idx = base + (int64_t)u * kVecThreads;
+    if (idx < L) {
+      const Node<N1> n = node_at<N1>(b, idx);
+      if (!n.boundary) {
+        const double wa = gather_copies<N1>(w, b, n, idx);
+        const double rt = ld_once(r + idx) - alpha * wa;
+        r[idx] = rt;
+        const double c = n.inv_mult();
+        rr += c * rt * rt;
+        rz += c * rt * (ld_once(minv + idx) * rt);
+      }
+    }
+  }
+  TileSums t;
+  t.a = block_sum<kVecThreads>(rr, sred);
+  t.b = block_sum<kVecThreads>(rz, sred);
+  return t;
+}
+
 template <int N1, typename TV>
 __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__restrict__ r,
                                           const TV *__restrict__ w, const TV *__restrict__ minv,
                                           double alpha, double *sA, double *sred,
                                           int tid) {
-  using U = UpdTile<N1>;
+  using U = UpdTile<N1, TV>;
+  if constexpr (U::LINEAR)
+    return cg_update_tile_linear<N1>(b, tile, r, w, minv, alpha, sred, tid);
   constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
   const bool act = tid < U::THREADS;
   const int t = act ? tid : 0;
@@ -158,11 +195,12 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
     upd_column<N1, KN, TV>(w, xc, kb, hy, yoff, z_lo, z_hi, dz, X);
   }
   if constexpr (U::EPT > 1) {
+    // slot (element, thread's plane range, plane, column)
 #pragma unroll
-    for (int kk = 0; kk < KN; ++kk) sA[el * NP + kk * COLS + col] = A[kk];
+    for (int kk = 0; kk < KN; ++kk) sA[((el * U::KS + ks) * KN + kk) * COLS + col] = A[kk];
     __syncthreads();
     if (x_in) {
-      const int xo = (i == 0 ? el - 1 : el + 1) * NP + j * N1 + (N - i);
+      const int xo = ((i == 0 ? el - 1 : el + 1) * U::KS + ks) * KN * COLS + j * N1 + (N - i);
 #pragma unroll
       for (int kk = 0; kk < KN; ++kk) X[kk] = sA[xo + kk * COLS];
     }
@@ -188,8 +226,8 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
     }
   }
   TileSums ts;
-  ts.a = block_sum<kVecThreads>(rr, sred);
-  ts.b = block_sum<kVecThreads>(rz, sred);
+  ts.a = block_sum<U::BLOCK>(rr, sred);
+  ts.b = block_sum<U::BLOCK>(rz, sred);
   return ts;
 }
 

@@ -82,28 +82,35 @@ inline int64_t vec_num_blocks(int64_t n) { return (n + kVecTile - 1) / kVecTile;
 inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) / 8); }
 
 // Tiles of the CG update (the gather-scatter pulled into r -= alpha w) are
-// element-aligned: upd_ept consecutive elements per tile with upd_ks threads
-// per (i, j) column, or one element in upd_kp plane ranges at the highest
-// orders; a tile fits kVecThreads threads and, with several elements, keeps
-// them in kUpdLds doubles of LDS.
+// element-aligned: upd_ept consecutive elements with upd_ks threads per
+// (i, j) column, over all planes or, at the highest orders, over one of
+// upd_kp plane ranges.  Up to order 7 a tile fills 256 threads; above, it
+// holds two elements (up to 512 threads).  The FP64 update from order 9 up
+// keeps linear streaming tiles of kVecTile entries (measured faster there).
 __host__ __device__ constexpr int upd_ks(int n1) {
   return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11) ? 2 : 1);
 }
 __host__ __device__ constexpr int upd_ept(int n1) {
-  return upd_ks(n1) * n1 * n1 > kVecThreads / 2 ? 1 : kVecThreads / (upd_ks(n1) * n1 * n1);
+  return n1 >= 9 ? 2 : kVecThreads / (upd_ks(n1) * n1 * n1);
 }
 __host__ __device__ constexpr int upd_kp(int n1) { return n1 >= 12 ? 2 : 1; }
-constexpr int kUpdLds = 2048;
-inline int64_t upd_num_tiles(const Box &b) {
+__host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
+inline int64_t upd_num_tiles(const Box &b, bool f64) {
   const int n1 = b.N + 1;
+  if (upd_linear(n1, f64)) return vec_num_blocks(b.L());
   return (b.E() + upd_ept(n1) - 1) / upd_ept(n1) * upd_kp(n1);
 }
-// Launch size and partial count of the update (a multiple of the XCD count).
-inline int64_t upd_grid_blocks(const Box &b) { return 8 * ((upd_num_tiles(b) + 7) / 8); }
+// Launch size of the update (a multiple of the XCD count).
+inline int64_t upd_grid_blocks(const Box &b, bool f64) {
+  return 8 * ((upd_num_tiles(b, f64) + 7) / 8);
+}
 // Partials a solve's streaming reductions need room for.
 inline int64_t stream_partials(const Box &b) {
-  const int64_t v = vec_grid_blocks(b.L()), u = upd_grid_blocks(b);
-  return v > u ? v : u;
+  int64_t v = vec_grid_blocks(b.L());
+  const int64_t u64 = upd_grid_blocks(b, true), u32 = upd_grid_blocks(b, false);
+  if (u64 > v) v = u64;
+  if (u32 > v) v = u32;
+  return v;
 }
 
 // What the gather kernel writes at a node: the sum of its copies
@@ -145,7 +152,7 @@ struct BatchSlot {
   int phase;  // SlotPhase, written by the device
   int inner_total;
   int inner_max;
-  int utiles;  // update tiles (upd_num_tiles); partials of the CG update
+  int utiles;  // update tiles of its CG update (upd_num_tiles); partials of that update
   double eta2;
   int64_t E, L;
   const double *D, *G, *b;

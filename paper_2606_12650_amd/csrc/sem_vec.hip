@@ -70,12 +70,12 @@ __global__ void __launch_bounds__(kFinThreads)
 }
 
 template <int N1, typename TV>
-__global__ void __launch_bounds__(kVecThreads)
+__global__ void __launch_bounds__((UpdTile<N1, TV>::BLOCK))
     cg_update_kernel(Box b, int64_t ntiles, TV *__restrict__ r, const TV *__restrict__ w,
                      const TV *__restrict__ minv, CgState *__restrict__ st,
                      double *__restrict__ part_rr, double *__restrict__ part_rz) {
-  __shared__ double sred[kVecThreads / 64];
-  __shared__ double sA[UpdTile<N1>::EPT > 1 ? kUpdLds : 1];
+  __shared__ double sred[UpdTile<N1, TV>::BLOCK / 64];
+  __shared__ double sA[UpdTile<N1, TV>::LDS];
   if (st->done) return;
   const double alpha = st->alpha;
   const int64_t tile = xcd_tile(ntiles);
@@ -222,6 +222,28 @@ __global__ void __launch_bounds__(kFinThreads)
 }
 
 inline dim3 vec_grid(int64_t n) { return dim3((unsigned)vec_num_blocks(n)); }
+
+template <typename TV>
+hipError_t update_typed(const Box &b, TV *r, const TV *w, const TV *minv, CgState *st,
+                        double *part_rr, double *part_rz, hipStream_t s) {
+  if (b.E() == 0) return hipSuccess;
+  const bool f64 = sizeof(TV) == 8;
+  const int64_t nt = upd_num_tiles(b, f64);
+  const dim3 grid((unsigned)upd_grid_blocks(b, f64));
+  switch (b.N) {
+#define UCASE(n_)                                                                        \
+  case n_:                                                                               \
+    hipLaunchKernelGGL((cg_update_kernel<n_ + 1, TV>), grid, dim3(UpdTile<n_ + 1, TV>::BLOCK), 0, \
+                       s, b, nt, r, w, minv, st, part_rr, part_rz);                      \
+    break;
+    UCASE(1) UCASE(2) UCASE(3) UCASE(4) UCASE(5) UCASE(6)
+    UCASE(7) UCASE(8) UCASE(9) UCASE(10) UCASE(11) UCASE(12)
+#undef UCASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 inline dim3 xcd_vec_grid(int64_t n) { return dim3((unsigned)vec_grid_blocks(n)); }
 
 }  // namespace
@@ -336,20 +358,12 @@ hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part
 
 hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  if (b.E() == 0) return hipSuccess;
-  const int64_t nt = upd_num_tiles(b);
-  DISPATCH_N_MODE(b, double, cg_update_kernel, dim3((unsigned)upd_grid_blocks(b)), dim3(kVecThreads),
-                  0, s, b, nt, r, w, minv, st, part_rr, part_rz);
-  return hipGetLastError();
+  return update_typed<double>(b, r, w, minv, st, part_rr, part_rz, s);
 }
 
 hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
                                 CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  if (b.E() == 0) return hipSuccess;
-  const int64_t nt = upd_num_tiles(b);
-  DISPATCH_N_MODE(b, float, cg_update_kernel, dim3((unsigned)upd_grid_blocks(b)), dim3(kVecThreads),
-                  0, s, b, nt, r, w, minv, st, part_rr, part_rz);
-  return hipGetLastError();
+  return update_typed<float>(b, r, w, minv, st, part_rr, part_rz, s);
 }
 
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
