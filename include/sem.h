@@ -84,8 +84,8 @@ typedef struct {
                                run (FP64 and the low-precision copy):
                                0: the faster one for the order and precision
                                   as measured on MI355X (matrix cores from
-                                  N = 7 in FP64 and from N = 11 in FP32/BF16,
-                                  vector ALUs below);
+                                  N = 7 in FP64 and FP32 and from N = 9 in
+                                  BF16, vector ALUs below);
                                SEM_FLAG_MFMA: always the matrix-core kernel
                                   (D contractions as f64 MFMA, or f32 / bf16
                                   MFMA with FP32 accumulation);

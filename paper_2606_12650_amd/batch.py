@@ -30,7 +30,7 @@ def default_epb(order: int, prec: str = "f64") -> int:
     """The library's default elements per operator item (the single-solve tile
     of the element kernel that order and precision run by default)."""
     n1 = order + 1
-    if order >= {"f64": 7, "f32": 8, "bf16": 9}[prec]:  # matrix-core tile
+    if order >= {"f64": 7, "f32": 7, "bf16": 9}[prec]:  # matrix-core tile
         nt = (n1 * n1 + 15) // 16
         return 1 if nt >= 8 else 8 // nt
     return 1 if n1 * n1 >= 128 else 128 // (n1 * n1)

@@ -134,11 +134,43 @@ __device__ inline int slot_bin(const BatchSlot &S) {
   return cls < 0 ? -1 : batch_bin(cls, S.N);
 }
 
+// Ordered compaction of one work list by one wave: the slots q < ms with
+// count(q) > 0 in ascending order, the exclusive prefix sums of their counts
+// (ballots and a wave scan) and [count, total].
+template <class C>
+__device__ inline void build_list(const BatchSched &sc, int b, int ms, C count) {
+  const int lane = threadIdx.x & 63;
+  int off = 0, run = 0;
+  for (int c = 0; c < ms; c += 64) {
+    const int q = c + lane;
+    const int n = q < ms ? count(q) : 0;
+    const bool in = n > 0;
+    const unsigned long long m = __ballot(in);
+    const int pos = __popcll(m & ((1ull << lane) - 1ull));
+    int x = n;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (in) {
+      sc.slot[b * ms + off + pos] = q;
+      sc.prefix[b * (ms + 1) + off + pos] = run + x - n;
+    }
+    off += __popcll(m);
+    run += __shfl(x, 63);
+  }
+  if (lane == 0) {
+    sc.prefix[b * (ms + 1) + off] = run;
+    sc.meta[2 * b] = off;
+    sc.meta[2 * b + 1] = run;
+  }
+}
+
 __global__ void __launch_bounds__(kSchedThreads)
     batch_schedule_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, BatchTiles tiles) {
   __shared__ int s_bin[kBatchMaxSlots];
   __shared__ int s_cnt[kBatchMaxSlots];
-  __shared__ int s_vt[kBatchMaxSlots];
   const int ms = sc.max_slots;
   for (int q = threadIdx.x; q < ms; q += blockDim.x) {
     const BatchSlot &S = slots[q];
@@ -146,56 +178,51 @@ __global__ void __launch_bounds__(kSchedThreads)
     s_bin[q] = b;
     const int epb = b < 0 ? 1 : tiles.epb[b / kBatchOrders][S.N];
     s_cnt[q] = b < 0 ? 0 : (int)((S.E + epb - 1) / epb);
-    // streaming list of its family (FP64 or mixed), as a signed count
-    const int vt = (S.active && S.phase != kPhaseFinished) ? S.vtiles : 0;
-    s_vt[q] = S.mixed ? -vt : vt;
   }
   __syncthreads();
-  // one wave per bin: ordered compaction by ballot, prefix sums by a wave scan
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // one wave per list
+  const int wave = threadIdx.x >> 6;
   for (int b = wave; b < kBatchLists; b += kSchedThreads / 64) {
-    int off = 0, run = 0;
-    for (int c = 0; c < ms; c += 64) {
-      const int q = c + lane;
-      int n = 0;
-      if (q < ms) {
-        if (b >= kBatchUpdLists) {
-          // update tiles of the slots in the operator bins of this family and order
-          const int fam = (b - kBatchUpdLists) / kBatchOrders;
-          const int N = b - kBatchUpdLists - fam * kBatchOrders + 1;
-          const int sb = s_bin[q];
-          const bool in_fam = fam == 0 ? sb == batch_bin(0, N)
-                                       : (sb == batch_bin(1, N) || sb == batch_bin(2, N));
-          n = in_fam ? slots[q].utiles : 0;
-        } else if (b == kBatchBins) {
-          n = max(s_vt[q], 0);
-        } else if (b == kBatchBins + 1) {
-          n = max(-s_vt[q], 0);
-        } else {
-          n = s_bin[q] == b ? s_cnt[q] : 0;
-        }
-      }
-      const bool in = n > 0;
-      const unsigned long long m = __ballot(in);
-      const int pos = __popcll(m & ((1ull << lane) - 1ull));
-      int x = n;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-      }
-      if (in) {
-        sc.slot[b * ms + off + pos] = q;
-        sc.prefix[b * (ms + 1) + off + pos] = run + x - n;
-      }
-      off += __popcll(m);
-      run += __shfl(x, 63);
+    if (b >= kBatchUpdLists) {
+      // update tiles of the slots in the operator bins of this family and order
+      const int fam = (b - kBatchUpdLists) / kBatchOrders;
+      const int N = b - kBatchUpdLists - fam * kBatchOrders + 1;
+      build_list(sc, b, ms, [&](int q) {
+        const int sb = s_bin[q];
+        const bool in_fam = fam == 0 ? sb == batch_bin(0, N)
+                                     : (sb == batch_bin(1, N) || sb == batch_bin(2, N));
+        return in_fam ? slots[q].utiles : 0;
+      });
+    } else if (b == kBatchResidList) {
+      // streaming tiles of the slots whose outer operator runs (class 3)
+      build_list(sc, b, ms, [&](int q) {
+        const int sb = s_bin[q];
+        return (sb >= 0 && sb / kBatchOrders == 3) ? slots[q].vtiles : 0;
+      });
+    } else if (b < kBatchBins) {
+      build_list(sc, b, ms, [&](int q) { return s_bin[q] == b ? s_cnt[q] : 0; });
     }
-    if (lane == 0) {
-      sc.prefix[b * (ms + 1) + off] = run;
-      sc.meta[2 * b] = off;
-      sc.meta[2 * b + 1] = run;
-    }
+  }
+}
+
+// The two finishing lists, rebuilt after the beta launch has set this
+// iteration's phases: FP64 solves that stopped (x owes alpha p) and mixed
+// solves whose inner solve ended or whose inner solve restarts.
+__global__ void __launch_bounds__(128)
+    batch_fin_schedule_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
+  const int wave = threadIdx.x >> 6;
+  if (wave == 0) {
+    build_list(sc, kBatchFinList, sc.max_slots, [&](int q) {
+      const BatchSlot &S = slots[q];
+      return (S.active && S.mixed == 0 && S.phase == kPhaseFp64Done && S.st->done_stage == 2)
+                 ? S.vtiles : 0;
+    });
+  } else {
+    build_list(sc, kBatchFinList + 1, sc.max_slots, [&](int q) {
+      const BatchSlot &S = slots[q];
+      return (S.active && S.mixed != 0 &&
+              (S.phase == kPhaseInnerDone || S.phase == kPhaseRestart)) ? S.vtiles : 0;
+    });
   }
 }
 
@@ -270,13 +297,16 @@ __global__ void __launch_bounds__((OpCfg<N1, EPB, MFMA>::THREADS))
 
 // ------------------------------------------------------------- streaming
 
+// The per-item functions below return false when the slot has no work of
+// their kind in this iteration (the walk then skips its remaining items).
+
 // The CG update of one update tile of an FP64 solve (MIXED = false) or of
 // an inner solve's FP32 vectors (MIXED = true).
 template <int N1, bool MIXED>
-__device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double *sA,
+__device__ __forceinline__ bool update_item(const BatchSlot &S, int tile, double *sA,
                                             double *sred) {
   if constexpr (!MIXED) {
-    if (S.phase != kPhaseFp64 || S.st->done != kRunning || tile >= S.utiles) return;
+    if (S.phase != kPhaseFp64 || S.st->done != kRunning || tile >= S.utiles) return false;
     const TileSums t = cg_update_tile<N1, double>(S.box, tile, S.r, S.w, S.minv, S.st->alpha,
                                                   sA, sred, (int)threadIdx.x);
     if (threadIdx.x == 0) {
@@ -284,7 +314,7 @@ __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double
       S.part_rz[tile] = t.b;
     }
   } else {
-    if (S.phase != kPhaseInner || S.st_in->done != kRunning || tile >= S.utiles) return;
+    if (S.phase != kPhaseInner || S.st_in->done != kRunning || tile >= S.utiles) return false;
     const TileSums t = cg_update_tile<N1, float>(S.box, tile, S.rin, S.win, S.minv32,
                                                  S.st_in->alpha, sA, sred, (int)threadIdx.x);
     if (threadIdx.x == 0) {
@@ -292,14 +322,16 @@ __device__ __forceinline__ void update_item(const BatchSlot &S, int tile, double
       S.part_rz[tile] = t.b;
     }
   }
+  return true;
 }
 
 // The FP64 true residual of a mixed solve's outer step on one streaming tile.
 template <int N1>
-__device__ __forceinline__ void residual_item(const BatchSlot &S, int tile, double *sred) {
-  if (S.phase != kPhaseOuterOp || tile >= S.vtiles) return;
+__device__ __forceinline__ bool residual_item(const BatchSlot &S, int tile, double *sred) {
+  if (S.phase != kPhaseOuterOp || tile >= S.vtiles) return false;
   const double rr = residual_tile<N1>(S.box, S.L, tile, S.b, S.w, S.r, sred);
   if (threadIdx.x == 0) S.part_rr[tile] = rr;
+  return true;
 }
 
 // The end of an FP64 solve (x += alpha p), the correction of a mixed solve
@@ -307,9 +339,9 @@ __device__ __forceinline__ void residual_item(const BatchSlot &S, int tile, doub
 // e = p = 0 and the partials of its scalars); these phases are set by the
 // beta launch of the same iteration.
 template <int N1, bool MIXED>
-__device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double *sred) {
+__device__ __forceinline__ bool finish_item(const BatchSlot &S, int tile, double *sred) {
   if constexpr (!MIXED) {
-    if (S.phase != kPhaseFp64Done || S.st->done_stage != 2) return;
+    if (S.phase != kPhaseFp64Done || S.st->done_stage != 2) return false;
     const double alpha = S.st->alpha;
     const int64_t base = (int64_t)tile * kVecTile + threadIdx.x;
 #pragma unroll
@@ -329,12 +361,17 @@ __device__ __forceinline__ void finish_item(const BatchSlot &S, int tile, double
         S.part_rz[tile] = t.a;
         S.part_rr[tile] = t.b;
       }
+    } else {
+      return false;
     }
   }
+  return true;
 }
 
 // A persistent walk over the items of one work list: each work-group takes
-// a contiguous range of its XCD's share and calls f(slot, item) per item.
+// a contiguous range of its XCD's share and calls f(slot, item) per item;
+// when f returns false the slot has nothing to do in this launch and the
+// walk jumps to the next slot.
 template <class F>
 __device__ __forceinline__ void walk_list(const BatchSlot *__restrict__ slots, const BatchSched &sc,
                                           int list, F f) {
@@ -355,7 +392,7 @@ __device__ __forceinline__ void walk_list(const BatchSlot *__restrict__ slots, c
       first = next;
       next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
     }
-    f(slots[__builtin_amdgcn_readfirstlane(sl[k])], w - first);
+    if (!f(slots[__builtin_amdgcn_readfirstlane(sl[k])], w - first)) w = next - 1;
   }
 }
 
@@ -370,7 +407,7 @@ __global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
   __shared__ double sred[BatchUpd<N1, MIXED>::BLOCK / 64];
   __shared__ double sA[BatchUpd<N1, MIXED>::LDS];
   walk_list(slots, sc, list, [&](const BatchSlot &S, int tile) {
-    update_item<N1, MIXED>(S, tile, sA, sred);
+    return update_item<N1, MIXED>(S, tile, sA, sred);
   });
 }
 
@@ -378,16 +415,16 @@ __global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
 __global__ void __launch_bounds__(kVecThreads)
     batch_resid_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
   __shared__ double sred[kVecThreads / 64];
-  walk_list(slots, sc, kBatchBins + 1, [&](const BatchSlot &S, int tile) {
+  walk_list(slots, sc, kBatchResidList, [&](const BatchSlot &S, int tile) {
     switch (S.N) {
 #define RCASE(n_) \
   case n_:        \
-    residual_item<n_ + 1>(S, tile, sred); break;
+    return residual_item<n_ + 1>(S, tile, sred);
       RCASE(1) RCASE(2) RCASE(3) RCASE(4) RCASE(5) RCASE(6)
       RCASE(7) RCASE(8) RCASE(9) RCASE(10) RCASE(11)
 #undef RCASE
       default:
-        break;
+        return false;
     }
   });
 }
@@ -398,16 +435,16 @@ template <bool MIXED>
 __global__ void __launch_bounds__(kVecThreads)
     batch_fin_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
   __shared__ double sred[kVecThreads / 64];
-  walk_list(slots, sc, kBatchBins + (MIXED ? 1 : 0), [&](const BatchSlot &S, int tile) {
+  walk_list(slots, sc, kBatchFinList + (MIXED ? 1 : 0), [&](const BatchSlot &S, int tile) {
     switch (S.N) {
 #define FCASE(n_) \
   case n_:        \
-    finish_item<n_ + 1, MIXED>(S, tile, sred); break;
+    return finish_item<n_ + 1, MIXED>(S, tile, sred);
       FCASE(1) FCASE(2) FCASE(3) FCASE(4) FCASE(5) FCASE(6)
       FCASE(7) FCASE(8) FCASE(9) FCASE(10) FCASE(11)
 #undef FCASE
       default:
-        break;
+        return false;
     }
   });
 }
@@ -641,6 +678,7 @@ hipError_t launch_batch_iteration(BatchSlot *slots, int max_slots, const BatchSc
   if (mix)
     hipLaunchKernelGGL(batch_resid_kernel, dim3(g->resid), dim3(kVecThreads), 0, s, slots, sched);
   hipLaunchKernelGGL(batch_beta_kernel, dim3(max_slots), dim3(kFinThreads), 0, s, slots);
+  hipLaunchKernelGGL(batch_fin_schedule_kernel, dim3(1), dim3(128), 0, s, slots, sched);
   if (f64)
     hipLaunchKernelGGL((batch_fin_kernel<false>), dim3(g->fin[0]), dim3(kVecThreads), 0, s, slots,
                        sched);

@@ -85,20 +85,22 @@ inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) 
 // element-aligned: upd_ept consecutive elements with upd_ks threads per
 // (i, j) column, over all planes or, at the highest orders, over one of
 // upd_kp plane ranges.  Up to order 7 a tile fills 256 threads; above, it
-// holds two elements (up to 512 threads).  The FP64 update from order 9 up
-// keeps linear streaming tiles of kVecTile entries (measured faster there).
+// holds two elements in FP64 (up to 512 threads) and one in FP32.  The FP64
+// update from order 9 up keeps linear streaming tiles of kVecTile entries.
+// All of these choices are what measured faster on MI355X.
 __host__ __device__ constexpr int upd_ks(int n1) {
   return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11) ? 2 : 1);
 }
-__host__ __device__ constexpr int upd_ept(int n1) {
-  return n1 >= 9 ? 2 : kVecThreads / (upd_ks(n1) * n1 * n1);
+__host__ __device__ constexpr int upd_ept(int n1, bool f64) {
+  return n1 >= 9 ? (f64 ? 2 : 1) : kVecThreads / (upd_ks(n1) * n1 * n1);
 }
 __host__ __device__ constexpr int upd_kp(int n1) { return n1 >= 12 ? 2 : 1; }
 __host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
 inline int64_t upd_num_tiles(const Box &b, bool f64) {
   const int n1 = b.N + 1;
   if (upd_linear(n1, f64)) return vec_num_blocks(b.L());
-  return (b.E() + upd_ept(n1) - 1) / upd_ept(n1) * upd_kp(n1);
+  const int ept = upd_ept(n1, f64);
+  return (b.E() + ept - 1) / ept * upd_kp(n1);
 }
 // Launch size of the update (a multiple of the XCD count).
 inline int64_t upd_grid_blocks(const Box &b, bool f64) {
@@ -122,9 +124,10 @@ enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse 
 // Which element tile an operator runs by default, per arithmetic class (0 and
 // 3 FP64, 1 FP32, 2 BF16) and order N: the matrix-core tile (sem_ax_mfma.h)
 // where it measured faster on MI355X than the vector-unit tiles
-// (sem_ax_tile.h), i.e. from N = 7 in FP64, N = 8 in FP32 and N = 9 in BF16.
+// (sem_ax_tile.h) inside the CG, i.e. from N = 7 in FP64 and FP32 and from
+// N = 9 in BF16.
 __host__ __device__ constexpr bool op_uses_mfma(int cls, int N) {
-  return (cls == 0 || cls == 3) ? N >= 7 : (cls == 1 ? N >= 8 : N >= 9);
+  return (cls == 0 || cls == 3 || cls == 1) ? N >= 7 : N >= 9;
 }
 
 // Operator implementation request: the default above, or forced.
@@ -176,15 +179,18 @@ struct BatchStatus {
 // Operator work of a batched iteration is binned by class and order: class 0
 // is the FP64 CG iterations of FP64 solves, classes 1 and 2 the FP32 and BF16
 // inner iterations of mixed solves, class 3 the FP64 true-residual operator
-// of their outer steps.  Lists kBatchBins and kBatchBins + 1 hold the
-// streaming tiles of every unfinished FP64 solve and mixed solve; after them
-// come the update tiles of the CG update, per order, of the FP64 solves
-// (family 0, the slots of bin (0, N)) and of the inner solves (family 1, bins
-// (1, N) and (2, N)).
+// of their outer steps.  Lists kBatchFinList and kBatchFinList + 1 hold the
+// streaming tiles of the FP64 and mixed solves whose phase ends this
+// iteration (rebuilt after the beta launch), kBatchResidList those of the
+// mixed solves computing an outer true residual; after them come the update
+// tiles of the CG update, per order, of the FP64 solves (family 0, the slots
+// of bin (0, N)) and of the inner solves (family 1, bins (1, N) and (2, N)).
 constexpr int kBatchOrders = 11;  // batches take orders 1..11
 constexpr int kBatchClasses = 4;
 constexpr int kBatchBins = kBatchClasses * kBatchOrders;
-constexpr int kBatchUpdLists = kBatchBins + 2;
+constexpr int kBatchFinList = kBatchBins;
+constexpr int kBatchResidList = kBatchBins + 2;
+constexpr int kBatchUpdLists = kBatchBins + 3;
 constexpr int kBatchLists = kBatchUpdLists + 2 * kBatchOrders;
 constexpr int kBatchMaxSlots = 4096;
 __host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }

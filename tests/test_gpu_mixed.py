@@ -97,6 +97,24 @@ def test_mixed_cg_small(prec, mesh, N, mfma):
     print(f"[mixed] FP64 iterations {r64.iters}")
 
 
+@pytest.mark.parametrize("N", list(range(1, 13)))
+def test_mixed_cg_all_orders(N):
+    """FP32 inner-outer CG at every order (the FP32 CG update at each order's
+    tile shape) on meshes with partial update tiles."""
+    mesh = (5, 3, 2) if N <= 7 else (3, 2, 3)
+    pr = op.Problem(*mesh, N, 0.05)
+    b = workload.continuous_rhs(80 + N, *mesh, N)
+    xr, _ = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, rtol=1e-12)
+    A = sem.SemOperator(*mesh, N, 0.05, lowprec="f32", device=DEV)
+    x, res = A.cg(torch.from_numpy(b).to(DEV), rtol=1e-8, mixed=True)
+    assert res.status == 0 and res.rel_res <= 1e-8
+    xv = x.cpu().numpy()
+    c = pr.c.reshape(-1)
+    err = math.sqrt(np.sum(c * (xv - xr.reshape(-1)) ** 2) / np.sum(c * xr.reshape(-1) ** 2))
+    assert err <= 1e-5
+    assert opcg.true_rel_residual(pr.ax, pr.shape4(b), pr.shape4(xv), pr.c) <= 1e-8 * (1 + 1e-3)
+
+
 def test_mixed_cg_repeatable_and_graph_stream():
     nx, ny, nz, N = 4, 4, 4, 7
     A = sem.SemOperator(nx, ny, nz, N, 0.05, lowprec="f32", device=DEV)

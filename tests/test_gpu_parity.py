@@ -238,6 +238,33 @@ def test_cg_tolerance_mode(mesh, N, every, mfma):
     assert _c_norm(x - xr.reshape(-1), pr.c) / _c_norm(xr, pr.c) <= 1e-5
 
 
+@pytest.mark.parametrize("N", list(range(1, 13)))
+def test_cg_all_orders_ragged(N):
+    """20 FP64 PCG iterations at every order on meshes whose element count and
+    x extent are not multiples of the update tiles' element groups (partial
+    last tiles, tiles that straddle element rows)."""
+    mesh = (5, 3, 2) if N <= 7 else (3, 2, 3)
+    pr = op.Problem(*mesh, N, 0.05)
+    b = workload.continuous_rhs(60 + N, *mesh, N)
+    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, fixed_iter=20)
+    A = sem.SemOperator(*mesh, N, 0.05, device=DEV)
+    xg, res = A.cg(_gpu(b), fixed_iter=20)
+    assert res.iters == 20 and res.status == 0
+    x = _cpu(xg)
+    assert _c_norm(x - xr.reshape(-1), pr.c) / _c_norm(xr, pr.c) <= 1e-9
+    # small systems converge exactly within 20 iterations: past that the
+    # residuals are rounding noise on both sides
+    assert (abs(res.rel_res - info["rel_res"]) <= 1e-6 * info["rel_res"]
+            or max(res.rel_res, info["rel_res"]) <= 1e-13)
+    # continuity: every copy of a node holds the same bits of x
+    gid = pr.gid.reshape(-1)
+    hi = np.full(gid.max() + 1, -np.inf)
+    lo = np.full(gid.max() + 1, np.inf)
+    np.maximum.at(hi, gid, x)
+    np.minimum.at(lo, gid, x)
+    assert np.array_equal(hi, lo)
+
+
 def test_cg_breakdown_and_cap_are_reported():
     nx = ny = nz = 2
     N = 4
