@@ -420,6 +420,14 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         copy_s = c0.elapsed_time(c1) / 1e3 / 10
         copy_gbs = 2 * src.numel() * 8 / copy_s / 1e9
+        # this library's own streaming kernel (vec_axpy: read x and y, write y)
+        sem.vec_axpy(0.5, src, dst)
+        c0.record(stream)
+        for _ in range(10):
+            sem.vec_axpy(0.5, src, dst)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        stream_gbs = 3 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3 / 10) / 1e9
         del src, dst
 
         # ---- precision form: inner-outer CG with the FP32 / BF16 operator
@@ -515,6 +523,8 @@ def main(argv=None) -> int:
         "ax_gdofs": gdof / ax_s / 1e9,
         "copy_gbs_measured": copy_gbs,
         "ax_frac_of_measured_copy": achieved / copy_gbs,
+        "stream_gbs_measured": stream_gbs,
+        "ax_frac_of_measured_stream": achieved / stream_gbs,
         "ax_masked_gdofs": gdof / axm_s / 1e9,
         "roofline": {
             "kernel": "ax_mfma_kernel<8, PrecF64, false> (sem_ax element operator, N=7: the "
