@@ -185,9 +185,23 @@ __global__ void __launch_bounds__(kVecThreads)
 }
 
 // ------------------------------------------------------------ generic vectors
+// Full tiles issue every load before the first use (the loads of all items
+// are in flight together); the last, partial tile takes the entry-by-entry
+// path.  Both read x and y once: non-temporal.
 __global__ void __launch_bounds__(kVecThreads)
     axpy_kernel(int64_t n, double alpha, const double *__restrict__ x, double *__restrict__ y) {
   const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
+  if ((int64_t)(blockIdx.x + 1) * kVecTile <= n) {
+    double xv[kVecItems], yv[kVecItems];
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+      xv[u] = ld_once(x + base + (int64_t)u * kVecThreads);
+      yv[u] = ld_once(y + base + (int64_t)u * kVecThreads);
+    }
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) st_once(y + base + (int64_t)u * kVecThreads, fma(alpha, xv[u], yv[u]));
+    return;
+  }
 #pragma unroll
   for (int u = 0; u < kVecItems; ++u) {
     const int64_t idx = base + (int64_t)u * kVecThreads;
@@ -195,6 +209,8 @@ __global__ void __launch_bounds__(kVecThreads)
   }
 }
 
+// Per-thread sums in item order (the same order on both paths), then the
+// block tree.
 template <bool W>
 __global__ void __launch_bounds__(kVecThreads)
     dot_partial_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
@@ -202,12 +218,28 @@ __global__ void __launch_bounds__(kVecThreads)
   __shared__ double sred[kVecThreads / 64];
   const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
   double acc = 0.0;
+  if ((int64_t)(blockIdx.x + 1) * kVecTile <= n) {
+    double xv[kVecItems], yv[kVecItems], wv[kVecItems];
 #pragma unroll
-  for (int u = 0; u < kVecItems; ++u) {
-    const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < n) {
-      const double v = x[idx] * y[idx];
-      acc += W ? wt[idx] * v : v;
+    for (int u = 0; u < kVecItems; ++u) {
+      const int64_t idx = base + (int64_t)u * kVecThreads;
+      xv[u] = ld_once(x + idx);
+      yv[u] = ld_once(y + idx);
+      wv[u] = W ? ld_once(wt + idx) : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+      const double v = xv[u] * yv[u];
+      acc += W ? wv[u] * v : v;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < kVecItems; ++u) {
+      const int64_t idx = base + (int64_t)u * kVecThreads;
+      if (idx < n) {
+        const double v = x[idx] * y[idx];
+        acc += W ? wt[idx] * v : v;
+      }
     }
   }
   const double t = block_sum<kVecThreads>(acc, sred);
