@@ -145,6 +145,92 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
   return t;
 }
 
+// Where a thread of an element-column tile sits: its element, its (i, j)
+// column, its planes kb .. kb + KN - 1 and the copies its nodes have.
+template <int N1, typename TV>
+struct ColumnPos {
+  using U = UpdTile<N1, TV>;
+  static constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
+  bool live, hy, z_lo, z_hi, hx, x_in;
+  int el, ks, col, i, j, kb, ex, ey, ez;
+  int64_t yoff, dz, col0;
+  __device__ ColumnPos(const Box &b, int64_t tile, int tid) {
+    const bool act = tid < U::THREADS;
+    const int t = act ? tid : 0;
+    el = t / (U::KS * COLS);
+    const int rem = t - el * (U::KS * COLS);
+    ks = rem / COLS;
+    col = rem - ks * COLS;
+    i = col % N1;
+    j = col / N1;
+    const int64_t grp = tile / U::KP;
+    kb = (int)(tile - grp * U::KP) * U::KT + ks * KN;
+    const int64_t E = b.E();
+    const int64_t e_raw = grp * U::EPT + el;
+    live = act && e_raw < E;
+    const uint32_t e = (uint32_t)(e_raw < E ? e_raw : E - 1);
+    const uint32_t eyz = b.fdx.div(e);
+    ex = (int)(e - eyz * (uint32_t)b.nx);
+    const uint32_t ezz = b.fdy.div(eyz);
+    ey = (int)(eyz - ezz * (uint32_t)b.ny);
+    ez = (int)ezz;
+    const int64_t dy = (int64_t)b.nx * NP;
+    dz = dy * b.ny;
+    hy = (j == 0 && ey > 0) || (j == N && ey < b.ny - 1);
+    yoff = j == 0 ? (int64_t)N * N1 - dy : dy - (int64_t)N * N1;
+    z_lo = kb == 0 && ez > 0;
+    z_hi = kb <= N && kb + KN > N && ez < b.nz - 1;
+    hx = (i == 0 && ex > 0) || (i == N && ex < b.nx - 1);
+    x_in = U::EPT > 1 && hx && (i == 0 ? el > 0 : el < U::EPT - 1);
+    col0 = (int64_t)e * NP + col;
+  }
+  // Plane k (of this thread) is a node on the box boundary.
+  __device__ bool boundary(const Box &b, int k) const {
+    return (i == 0 && ex == 0) || (i == N && ex == b.nx - 1) || (j == 0 && ey == 0) ||
+           (j == N && ey == b.ny - 1) || (k == 0 && ez == 0) || (k == N && ez == b.nz - 1);
+  }
+  // 1 / multiplicity of the node at plane k.
+  __device__ double inv_mult(const Box &b, int k) const {
+    const bool hz = (k == 0 && ez > 0) || (k == N && ez < b.nz - 1);
+    const int m = (hx ? 2 : 1) * (hy ? 2 : 1) * (hz ? 2 : 1);
+    return m == 1 ? 1.0 : (m == 2 ? 0.5 : (m == 4 ? 0.25 : 0.125));
+  }
+};
+
+// S = the sum of all copies of each of the thread's nodes, as the pair tree
+// above.  With several elements per tile this holds a work-group barrier:
+// every thread of the work-group calls it.
+template <int N1, typename TV>
+__device__ inline void column_copy_sums(const ColumnPos<N1, TV> &p, const TV *__restrict__ w,
+                                        double *sA, double (&S)[UpdTile<N1, TV>::KN]) {
+  using U = UpdTile<N1, TV>;
+  constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
+  double A[KN];
+  upd_column<N1, KN, TV>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, A);
+  double X[KN];
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) X[kk] = 0.0;
+  if (p.hx && !p.x_in) {
+    // the x copy column lies in the neighbouring element of another tile
+    const int64_t xc = p.i == 0 ? p.col0 - NP + N : p.col0 + NP - N;
+    upd_column<N1, KN, TV>(w, xc, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, X);
+  }
+  if constexpr (U::EPT > 1) {
+    // slot (element, thread's plane range, plane, column)
+#pragma unroll
+    for (int kk = 0; kk < KN; ++kk) sA[((p.el * U::KS + p.ks) * KN + kk) * COLS + p.col] = A[kk];
+    __syncthreads();
+    if (p.x_in) {
+      const int xo =
+          ((p.i == 0 ? p.el - 1 : p.el + 1) * U::KS + p.ks) * KN * COLS + p.j * N1 + (N - p.i);
+#pragma unroll
+      for (int kk = 0; kk < KN; ++kk) X[kk] = sA[xo + kk * COLS];
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < KN; ++kk) S[kk] = p.hx ? A[kk] + X[kk] : A[kk];
+}
+
 template <int N1, typename TV>
 __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__restrict__ r,
                                           const TV *__restrict__ w, const TV *__restrict__ minv,
@@ -153,73 +239,25 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
   using U = UpdTile<N1, TV>;
   if constexpr (U::LINEAR)
     return cg_update_tile_linear<N1>(b, tile, r, w, minv, alpha, sred, tid);
-  constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
-  const bool act = tid < U::THREADS;
-  const int t = act ? tid : 0;
-  const int el = t / (U::KS * COLS), rem = t - el * (U::KS * COLS);
-  const int ks = rem / COLS, col = rem - ks * COLS;
-  const int i = col % N1, j = col / N1;
-  const int64_t grp = tile / U::KP;
-  const int kb = (int)(tile - grp * U::KP) * U::KT + ks * KN;  // first plane of the thread
-  const int64_t E = b.E();
-  const int64_t e_raw = grp * U::EPT + el;
-  const bool live = act && e_raw < E;
-  const uint32_t e = (uint32_t)(e_raw < E ? e_raw : E - 1);
-  const uint32_t eyz = b.fdx.div(e);
-  const int ex = (int)(e - eyz * (uint32_t)b.nx);
-  const uint32_t ezz = b.fdy.div(eyz);
-  const int ey = (int)(eyz - ezz * (uint32_t)b.ny), ez = (int)ezz;
-  const int64_t dy = (int64_t)b.nx * NP, dz = dy * b.ny;
-  const bool hy = (j == 0 && ey > 0) || (j == N && ey < b.ny - 1);
-  const int64_t yoff = j == 0 ? (int64_t)N * N1 - dy : dy - (int64_t)N * N1;
-  const bool z_lo = kb == 0 && ez > 0;
-  const bool z_hi = kb <= N && kb + KN > N && ez < b.nz - 1;
-  const bool hx = (i == 0 && ex > 0) || (i == N && ex < b.nx - 1);
-  const bool x_in = U::EPT > 1 && hx && (i == 0 ? el > 0 : el < U::EPT - 1);
-  const int64_t col0 = (int64_t)e * NP + col;
+  constexpr int N = U::N, COLS = U::COLS, KN = U::KN;
+  const ColumnPos<N1, TV> p(b, tile, tid);
   double rv[KN], mv[KN];
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
-    const int64_t a = col0 + (int64_t)min(kb + kk, N) * COLS;
+    const int64_t a = p.col0 + (int64_t)min(p.kb + kk, N) * COLS;
     rv[kk] = (double)ld_once(r + a);
     mv[kk] = (double)ld_once(minv + a);
   }
-  double A[KN];
-  upd_column<N1, KN, TV>(w, col0, kb, hy, yoff, z_lo, z_hi, dz, A);
-  double X[KN];
-#pragma unroll
-  for (int kk = 0; kk < KN; ++kk) X[kk] = 0.0;
-  if (hx && !x_in) {
-    // the x copy column lies in the neighbouring element of another tile
-    const int64_t xc = i == 0 ? col0 - NP + N : col0 + NP - N;
-    upd_column<N1, KN, TV>(w, xc, kb, hy, yoff, z_lo, z_hi, dz, X);
-  }
-  if constexpr (U::EPT > 1) {
-    // slot (element, thread's plane range, plane, column)
-#pragma unroll
-    for (int kk = 0; kk < KN; ++kk) sA[((el * U::KS + ks) * KN + kk) * COLS + col] = A[kk];
-    __syncthreads();
-    if (x_in) {
-      const int xo = ((i == 0 ? el - 1 : el + 1) * U::KS + ks) * KN * COLS + j * N1 + (N - i);
-#pragma unroll
-      for (int kk = 0; kk < KN; ++kk) X[kk] = sA[xo + kk * COLS];
-    }
-  }
-  const bool bx = (i == 0 && ex == 0) || (i == N && ex == b.nx - 1);
-  const bool by = (j == 0 && ey == 0) || (j == N && ey == b.ny - 1);
-  const int mxy = (hx ? 2 : 1) * (hy ? 2 : 1);
+  double S[KN];
+  column_copy_sums<N1, TV>(p, w, sA, S);
   double rr = 0.0, rz = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
-    const int k = kb + kk;
-    const bool bz = (k == 0 && ez == 0) || (k == N && ez == b.nz - 1);
-    if (live && k <= N && !bx && !by && !bz) {
-      const double S = hx ? A[kk] + X[kk] : A[kk];
-      const TV rt = (TV)(rv[kk] - alpha * S);
-      r[col0 + (int64_t)k * COLS] = rt;
-      const bool hz = (k == 0 && ez > 0) || (k == N && ez < b.nz - 1);
-      const int m = mxy * (hz ? 2 : 1);
-      const double c = m == 1 ? 1.0 : (m == 2 ? 0.5 : (m == 4 ? 0.25 : 0.125));
+    const int k = p.kb + kk;
+    if (p.live && k <= N && !p.boundary(b, k)) {
+      const TV rt = (TV)(rv[kk] - alpha * S[kk]);
+      r[p.col0 + (int64_t)k * COLS] = rt;
+      const double c = p.inv_mult(b, k);
       const double rd = (double)rt;
       rr += c * rd * rd;
       rz += c * rd * (mv[kk] * rd);

@@ -45,6 +45,32 @@ __global__ void __launch_bounds__(kVecThreads)
   }
 }
 
+// The same gather on element-column tiles (copies paired across faces, as
+// in the CG update), used where that tile is the update's tile.
+template <int N1, int MODE, typename T>
+__global__ void __launch_bounds__((UpdTile<N1, T>::BLOCK))
+    gather_col_kernel(Box b, int64_t ntiles, const T *__restrict__ wl, T *__restrict__ out) {
+  using U = UpdTile<N1, T>;
+  __shared__ double sA[U::LDS];
+  const int64_t tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const ColumnPos<N1, T> p(b, tile, (int)threadIdx.x);
+  double S[U::KN];
+  column_copy_sums<N1, T>(p, wl, sA, S);
+#pragma unroll
+  for (int kk = 0; kk < U::KN; ++kk) {
+    const int k = p.kb + kk;
+    if (p.live && k <= U::N) {
+      double v = S[kk];
+      if (MODE != kGatherAssembled && p.boundary(b, k))
+        v = 0.0;
+      else if (MODE == kGatherInverse)
+        v = 1.0 / v;
+      out[p.col0 + (int64_t)k * U::COLS] = (T)v;
+    }
+  }
+}
+
 // ------------------------------------------------------------ CG kernels
 template <int N1>
 __global__ void __launch_bounds__(kVecThreads)
@@ -314,41 +340,35 @@ inline dim3 xcd_vec_grid(int64_t n) { return dim3((unsigned)vec_grid_blocks(n));
     default: return hipErrorInvalidValue;                               \
   }
 
-#define DISPATCH_N_MODE_T(b, MODE, T, KERNEL, ...)                        \
-  switch ((b).N) {                                                        \
-    case 1: hipLaunchKernelGGL((KERNEL<2, MODE, T>), __VA_ARGS__); break;   \
-    case 2: hipLaunchKernelGGL((KERNEL<3, MODE, T>), __VA_ARGS__); break;   \
-    case 3: hipLaunchKernelGGL((KERNEL<4, MODE, T>), __VA_ARGS__); break;   \
-    case 4: hipLaunchKernelGGL((KERNEL<5, MODE, T>), __VA_ARGS__); break;   \
-    case 5: hipLaunchKernelGGL((KERNEL<6, MODE, T>), __VA_ARGS__); break;   \
-    case 6: hipLaunchKernelGGL((KERNEL<7, MODE, T>), __VA_ARGS__); break;   \
-    case 7: hipLaunchKernelGGL((KERNEL<8, MODE, T>), __VA_ARGS__); break;   \
-    case 8: hipLaunchKernelGGL((KERNEL<9, MODE, T>), __VA_ARGS__); break;   \
-    case 9: hipLaunchKernelGGL((KERNEL<10, MODE, T>), __VA_ARGS__); break;  \
-    case 10: hipLaunchKernelGGL((KERNEL<11, MODE, T>), __VA_ARGS__); break; \
-    case 11: hipLaunchKernelGGL((KERNEL<12, MODE, T>), __VA_ARGS__); break; \
-    case 12: hipLaunchKernelGGL((KERNEL<13, MODE, T>), __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                 \
+// The gather on the tiles the CG update of this order and precision uses.
+template <int N1, int MODE, typename T>
+void gather_launch(const Box &b, const T *wl, T *out, hipStream_t s) {
+  if constexpr (UpdTile<N1, T>::LINEAR) {
+    const int64_t L = b.L();
+    hipLaunchKernelGGL((gather_kernel<N1, MODE, T>), xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L,
+                       vec_num_blocks(L), wl, out);
+  } else {
+    const bool f64 = sizeof(T) == 8;
+    hipLaunchKernelGGL((gather_col_kernel<N1, MODE, T>), dim3((unsigned)upd_grid_blocks(b, f64)),
+                       dim3(UpdTile<N1, T>::BLOCK), 0, s, b, upd_num_tiles(b, f64), wl, out);
   }
+}
 
 template <typename T>
 hipError_t gather_typed(const Box &b, const T *wl, T *out, int mode, hipStream_t s) {
-  const int64_t L = b.L();
-  if (L == 0) return hipSuccess;
-  const int64_t nt = vec_num_blocks(L);
-  switch (mode) {
-    case kGatherAssembled:
-      DISPATCH_N_MODE_T(b, kGatherAssembled, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0,
-                        s, b, L, nt, wl, out);
-      break;
-    case kGatherMasked:
-      DISPATCH_N_MODE_T(b, kGatherMasked, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s,
-                        b, L, nt, wl, out);
-      break;
-    case kGatherInverse:
-      DISPATCH_N_MODE_T(b, kGatherInverse, T, gather_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0,
-                        s, b, L, nt, wl, out);
-      break;
+  if (b.L() == 0) return hipSuccess;
+  if (mode != kGatherAssembled && mode != kGatherMasked && mode != kGatherInverse)
+    return hipErrorInvalidValue;
+  switch (b.N) {
+#define GCASE(n_)                                                                 \
+  case n_:                                                                        \
+    if (mode == kGatherAssembled) gather_launch<n_ + 1, kGatherAssembled, T>(b, wl, out, s); \
+    else if (mode == kGatherMasked) gather_launch<n_ + 1, kGatherMasked, T>(b, wl, out, s);  \
+    else gather_launch<n_ + 1, kGatherInverse, T>(b, wl, out, s);                   \
+    break;
+    GCASE(1) GCASE(2) GCASE(3) GCASE(4) GCASE(5) GCASE(6)
+    GCASE(7) GCASE(8) GCASE(9) GCASE(10) GCASE(11) GCASE(12)
+#undef GCASE
     default:
       return hipErrorInvalidValue;
   }
