@@ -300,31 +300,6 @@ __global__ void __launch_bounds__((OpCfg<N1, EPB, MFMA>::THREADS))
 // The per-item functions below return false when the slot has no work of
 // their kind in this iteration (the walk then skips its remaining items).
 
-// The CG update of one update tile of an FP64 solve (MIXED = false) or of
-// an inner solve's FP32 vectors (MIXED = true).
-template <int N1, bool MIXED>
-__device__ __forceinline__ bool update_item(const BatchSlot &S, int tile, double *sA,
-                                            double *sred) {
-  if constexpr (!MIXED) {
-    if (S.phase != kPhaseFp64 || S.st->done != kRunning || tile >= S.utiles) return false;
-    const TileSums t = cg_update_tile<N1, double>(S.box, tile, S.r, S.w, S.minv, S.st->alpha,
-                                                  sA, sred, (int)threadIdx.x);
-    if (threadIdx.x == 0) {
-      S.part_rr[tile] = t.a;
-      S.part_rz[tile] = t.b;
-    }
-  } else {
-    if (S.phase != kPhaseInner || S.st_in->done != kRunning || tile >= S.utiles) return false;
-    const TileSums t = cg_update_tile<N1, float>(S.box, tile, S.rin, S.win, S.minv32,
-                                                 S.st_in->alpha, sA, sred, (int)threadIdx.x);
-    if (threadIdx.x == 0) {
-      S.part_rr[tile] = t.a;
-      S.part_rz[tile] = t.b;
-    }
-  }
-  return true;
-}
-
 // The FP64 true residual of a mixed solve's outer step on one streaming tile.
 template <int N1>
 __device__ __forceinline__ bool residual_item(const BatchSlot &S, int tile, double *sred) {
@@ -404,11 +379,62 @@ using BatchUpd = UpdTile<N1, typename std::conditional<MIXED, float, double>::ty
 template <int N1, bool MIXED>
 __global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
     batch_upd_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int list) {
+  using TV = typename std::conditional<MIXED, float, double>::type;
   __shared__ double sred[BatchUpd<N1, MIXED>::BLOCK / 64];
   __shared__ double sA[BatchUpd<N1, MIXED>::LDS];
-  walk_list(slots, sc, list, [&](const BatchSlot &S, int tile) {
-    return update_item<N1, MIXED>(S, tile, sA, sred);
-  });
+  const int cnt = sc.meta[2 * list], total = sc.meta[2 * list + 1];
+  int w0, w1;
+  xcd_block_range(total, &w0, &w1);
+  if (w0 >= w1) return;
+  const int *pre = sc.prefix + list * (sc.max_slots + 1);
+  const int *sl = sc.slot + list * sc.max_slots;
+  int k = __builtin_amdgcn_readfirstlane(find_slot(pre, cnt, w0));
+  int first = __builtin_amdgcn_readfirstlane(pre[k]);
+  int next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
+  // the slot's operands and state, loaded once per slot (not once per item)
+  int cur = -1, active = 0, ut = 0;
+  Box box;
+  TV *r = nullptr;
+  const TV *wv = nullptr, *minv = nullptr;
+  double alpha = 0.0;
+  double *prr = nullptr, *prz = nullptr;
+#pragma unroll 1
+  for (int w = w0; w < w1; ++w) {
+    while (w >= next) {
+      ++k;
+      first = next;
+      next = __builtin_amdgcn_readfirstlane(pre[k + 1]);
+    }
+    if (k != cur) {
+      cur = k;
+      const BatchSlot &S = slots[__builtin_amdgcn_readfirstlane(sl[k])];
+      const CgState *st = MIXED ? S.st_in : S.st;
+      active = __builtin_amdgcn_readfirstlane(
+          (S.phase == (MIXED ? kPhaseInner : kPhaseFp64) && st->done == kRunning) ? 1 : 0);
+      ut = S.utiles;
+      box = S.box;
+      alpha = st->alpha;
+      prr = S.part_rr;
+      prz = S.part_rz;
+      if constexpr (MIXED) {
+        r = S.rin; wv = S.win; minv = S.minv32;
+      } else {
+        r = S.r; wv = S.w; minv = S.minv;
+      }
+    }
+    if (!active) {  // the slot has no update in this iteration: skip its items
+      w = next - 1;
+      continue;
+    }
+    const int tile = w - first;
+    if (tile >= ut) continue;
+    const TileSums t = cg_update_tile<N1, TV>(box, tile, r, wv, minv, alpha, sA, sred,
+                                              (int)threadIdx.x);
+    if (threadIdx.x == 0) {
+      prr[tile] = t.a;
+      prz[tile] = t.b;
+    }
+  }
 }
 
 // The outer steps' true residuals of the mixed solves (every order).
