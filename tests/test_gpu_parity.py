@@ -75,6 +75,15 @@ def test_setup_fields_match_oracle(N):
 MFMA = pytest.mark.parametrize("mfma", [False, True], ids=["valu", "mfma"])
 
 
+def _same_on_copies(pr, v):
+    gid = pr.gid.reshape(-1)
+    hi = np.full(gid.max() + 1, -np.inf)
+    lo = np.full(gid.max() + 1, np.inf)
+    np.maximum.at(hi, gid, v.reshape(-1))
+    np.minimum.at(lo, gid, v.reshape(-1))
+    return bool(np.array_equal(hi, lo))
+
+
 @MFMA
 @pytest.mark.parametrize("N", list(range(1, 13)))
 @pytest.mark.parametrize("amp", [0.0, 0.05])
@@ -92,6 +101,9 @@ def test_ax_all_orders(N, amp, mfma):
     w = _cpu(A.ax(_gpu(u_cont), sem.MASKED)).reshape(pr.mask.shape)
     assert _rel_inf(w, ref) <= 1e-12
     assert np.all(w[pr.mask == 0] == 0.0)
+    # the assembled result holds the same bits on every copy of a node
+    wa = _cpu(A.ax(_gpu(u_disc), sem.ASSEMBLED))
+    assert _same_on_copies(pr, wa)
 
 
 @pytest.mark.parametrize("mesh,N", [((1, 1, 1), 1), ((1, 1, 1), 7), ((1, 1, 1), 12),
@@ -257,12 +269,7 @@ def test_cg_all_orders_ragged(N):
     assert (abs(res.rel_res - info["rel_res"]) <= 1e-6 * info["rel_res"]
             or max(res.rel_res, info["rel_res"]) <= 1e-13)
     # continuity: every copy of a node holds the same bits of x
-    gid = pr.gid.reshape(-1)
-    hi = np.full(gid.max() + 1, -np.inf)
-    lo = np.full(gid.max() + 1, np.inf)
-    np.maximum.at(hi, gid, x)
-    np.minimum.at(lo, gid, x)
-    assert np.array_equal(hi, lo)
+    assert _same_on_copies(pr, x)
 
 
 def test_cg_breakdown_and_cap_are_reported():
