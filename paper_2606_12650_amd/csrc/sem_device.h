@@ -139,16 +139,30 @@ __device__ inline double block_sum_any(double v, double *sred) {
 }
 
 // Sum of n partials in a fixed order by a block of T threads; valid in
-// thread 0.  Eight independent loads per thread are in flight at a time.
+// thread 0.  Each thread keeps eight running sums; the loads of four rounds
+// (32 per thread) are issued together before they are added, so a sum of up
+// to 32 T partials waits for memory once.
 template <int T>
 __device__ inline double sum_partials(const double *__restrict__ part, int64_t n, double *sred) {
+  constexpr int R = 4;
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t q = threadIdx.x; q < n; q += 8 * T) {
+  for (int64_t q = threadIdx.x; q < n; q += (int64_t)R * 8 * T) {
+    // rounds that hold any partial (the same for the whole block)
+    const int64_t q0 = q - threadIdx.x;
+    const int64_t left = (n - q0 + 8 * T - 1) / (8 * T);
+    const int rounds = left < R ? (int)left : R;
+    double v[R][8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t idx = q + (int64_t)u * T;
-      if (idx < n) a[u] += part[idx];
-    }
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t idx = q + (int64_t)(r * 8 + u) * T;
+        v[r][u] = (r < rounds && idx < n) ? part[idx] : 0.0;
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += v[r][u];
   }
   const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum<T>(t, sred);
