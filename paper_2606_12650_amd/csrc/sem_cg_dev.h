@@ -4,7 +4,8 @@
 //
 // *_tile functions process one streaming tile (kVecTile consecutive entries
 // of one element-local vector) with a work-group of kVecThreads and return
-// the tile's block sums in thread 0.  *_step functions finish a reduction
+// the tile's block sums in thread 0; the CG update's tiles are element-aligned
+// instead (UpdTile below).  *_step functions finish a reduction
 // over a solve's partials with a work-group of kFinThreads and advance the
 // solve's scalars (thread 0 writes).
 #pragma once

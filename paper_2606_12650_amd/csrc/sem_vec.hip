@@ -4,14 +4,15 @@
 //
 // Streaming kernels: one thread per 8 entries of an element-local vector,
 // 256 threads per work-group, every access a full-wave coalesced load or
-// store.  The gather-scatter is a pull: each node reads the copies of itself
-// held by neighbouring elements and sums them, so it fuses into the kernel
-// that consumes the assembled vector instead of making a pass of its own.
+// store.  The gather-scatter fuses into the kernel that consumes the
+// assembled vector instead of making a pass of its own: on element-column
+// tiles (copies paired across faces, sem_cg_dev.h) or, on linear tiles, as a
+// pull where each node reads the copies of itself held by neighbouring
+// elements.
 //
 // Reductions are deterministic: a work-group sums a fixed tile (wave64
-// butterfly, then its waves in order) and the partials are summed in tile
-// order, either by the last work-group to finish (single pass) or by a second
-// one-group launch.  Results depend only on the data and the sizes.
+// butterfly, then its waves in order) and a second one-group launch sums the
+// partials in tile order.  Results depend only on the data and the sizes.
 #include <hip/hip_runtime.h>
 
 #include "sem_cg_dev.h"
