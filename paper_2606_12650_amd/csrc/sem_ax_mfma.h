@@ -242,13 +242,22 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
       rv[m] = ld_once(r + idx[m]);
     }
   }
+  // G with the prologue's loads, or in FP64 from N = 8 (LATE_G) after the
+  // gradient, so that the gradient's MFMA accumulators and G are never live
+  // together: at N = 11 the kernel then holds 70 instead of 98 VGPRs, three
+  // work-groups per CU instead of two (measured on MI355X: CG iteration
+  // 466 -> 408 us; at N = 7 and for FP32 / BF16 the early loads were faster).
+  constexpr bool LATE_G = MfmaOps<P>::kF64 && N1 >= 9;
   TC gk[PPT][6];
+  auto load_gk = [&]() {
 #pragma unroll
-  for (int m = 0; m < PPT; ++m) {
-    const int64_t gi = okv[m] ? e * 6 * NP + (idx[m] - e * NP) : 0;
+    for (int m = 0; m < PPT; ++m) {
+      const int64_t gi = okv[m] ? e * 6 * NP + (idx[m] - e * NP) : 0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) gk[m][c] = load_g<P>(G + gi + (okv[m] ? (int64_t)c * NP : 0));
-  }
+      for (int c = 0; c < 6; ++c) gk[m][c] = load_g<P>(G + gi + (okv[m] ? (int64_t)c * NP : 0));
+    }
+  };
+  if constexpr (!LATE_G) load_gk();
   TC uk[PPT];
 #pragma unroll
   for (int m = 0; m < PPT; ++m) {
@@ -279,6 +288,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   }
   __syncthreads();  // every wave has read the operand tile
   if (mine) mfma_store<N1, P>(U, ut, 2, tile, l);
+  if constexpr (LATE_G) load_gk();
   __syncthreads();
 
   // metric at the flat-layout nodes; the weighted gradient is the next
