@@ -185,11 +185,14 @@ int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);
  * precision) advance together: each batched step runs one CG iteration of
  * every active solve.  A one-work-group schedule kernel first builds, on the
  * device, compact work lists of the solves that have operator work in each
- * (arithmetic class, order) bin and of the streaming tiles of every
- * unfinished solve; then one persistent operator launch per bin in use (each
- * compiled for its order), two streaming launches and one work-group per
- * solve for the scalars.  Every solve's arithmetic and reduction order are
- * those of sem_cg, so an FP64 solve gives the same bits in a batch as alone.
+ * (arithmetic class, order) bin, of their CG update tiles per order and of
+ * the streaming tiles of the solves in an outer-residual phase; then one
+ * persistent operator launch per bin in use and one update launch per order
+ * and family in use (each compiled for its order), one work-group per solve
+ * for the scalars, and the finishing launches over lists rebuilt after the
+ * scalars have set each solve's phase.  Every solve's arithmetic and
+ * reduction order are those of sem_cg, so an FP64 solve gives the same bits
+ * in a batch as alone.
  * Solves join and leave between steps (continuous batching); the step's
  * graph is captured again only when the set of bins in use or the tiles
  * change.  The batch holds no memory of its own on the device beyond its
@@ -198,8 +201,8 @@ int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);
 typedef struct sem_batch sem_batch;
 
 /* Workspace of a batch of up to max_slots solves (1..4096): slot table, the
- * schedule's work lists (34 bins of max_slots entries), status records.  0
- * for an invalid max_slots. */
+ * work lists (69 lists of max_slots entries with prefix sums), status
+ * records.  0 for an invalid max_slots. */
 size_t sem_batch_workspace_bytes(int max_slots);
 
 /* Create a batch in `dev_ws` (256-byte aligned).  Synchronous. */
