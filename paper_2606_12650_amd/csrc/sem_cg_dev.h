@@ -75,9 +75,9 @@ struct UpdTile {
   static constexpr int N = N1 - 1;
   static constexpr int COLS = N1 * N1;
   static constexpr int NP = COLS * N1;
-  static constexpr int KS = upd_ks(N1);    // threads per column
+  static constexpr int KS = upd_ks(N1, sizeof(TV) == 8);  // threads per column
   static constexpr int EPT = upd_ept(N1, sizeof(TV) == 8);  // elements per tile
-  static constexpr int KP = upd_kp(N1);    // tiles per element (plane ranges)
+  static constexpr int KP = upd_kp(N1, sizeof(TV) == 8);  // tiles per element (plane ranges)
   static constexpr int KT = (N1 + KP - 1) / KP;  // planes per tile
   static constexpr int KN = (KT + KS - 1) / KS;  // planes per thread
   static constexpr int THREADS = EPT * KS * COLS;

@@ -85,22 +85,25 @@ inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) 
 // element-aligned: upd_ept consecutive elements with upd_ks threads per
 // (i, j) column, over all planes or, at the highest orders, over one of
 // upd_kp plane ranges.  Up to order 7 a tile fills 256 threads; above, it
-// holds two elements in FP64 (up to 512 threads) and one in FP32.  The FP64
+// holds two elements in FP64 (up to 512 threads) and one in FP32 (at order
+// 11 with two threads per column rather than two plane ranges).  The FP64
 // update from order 9 up keeps linear streaming tiles of kVecTile entries.
 // All of these choices are what measured faster on MI355X.
-__host__ __device__ constexpr int upd_ks(int n1) {
-  return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11) ? 2 : 1);
+__host__ __device__ constexpr int upd_ks(int n1, bool f64) {
+  return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11 || (!f64 && n1 == 12)) ? 2 : 1);
 }
 __host__ __device__ constexpr int upd_ept(int n1, bool f64) {
-  return n1 >= 9 ? (f64 ? 2 : 1) : kVecThreads / (upd_ks(n1) * n1 * n1);
+  return n1 >= 9 ? (f64 ? 2 : 1) : kVecThreads / (upd_ks(n1, f64) * n1 * n1);
 }
-__host__ __device__ constexpr int upd_kp(int n1) { return n1 >= 12 ? 2 : 1; }
+__host__ __device__ constexpr int upd_kp(int n1, bool f64) {
+  return (n1 >= 13 || (f64 && n1 == 12)) ? 2 : 1;
+}
 __host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
 inline int64_t upd_num_tiles(const Box &b, bool f64) {
   const int n1 = b.N + 1;
   if (upd_linear(n1, f64)) return vec_num_blocks(b.L());
   const int ept = upd_ept(n1, f64);
-  return (b.E() + ept - 1) / ept * upd_kp(n1);
+  return (b.E() + ept - 1) / ept * upd_kp(n1, f64);
 }
 // Launch size of the update (a multiple of the XCD count).
 inline int64_t upd_grid_blocks(const Box &b, bool f64) {
