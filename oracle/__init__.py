@@ -22,6 +22,7 @@ pcg       Jacobi-preconditioned CG with multiplicity-weighted dots.
 dots      exactly rounded dot products (error-free transforms + fsum).
 brute     dense element matrices from a Legendre-Vandermonde basis.
 mixed     low-precision operator emulation and inner-outer refinement.
+gs        generic gather-scatter in compressed-row form (any id map).
 
 Parity status: every function here is pinned by a test of the CPU suite
 against a closed form, a library routine at higher precision, a dense brute
@@ -29,4 +30,4 @@ force or an invariant, except the iterates of the low-precision inner solver,
 which are "parity unpinned" (only their FP64 outer result is pinned).
 """
 
-from . import gll, mesh, operator, pcg, dots, brute, mixed  # noqa: F401
+from . import gll, mesh, operator, pcg, dots, brute, mixed, gs  # noqa: F401
