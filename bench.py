@@ -430,6 +430,34 @@ def main(argv=None) -> int:
         stream_gbs = 3 * src.numel() * 8 / (c0.elapsed_time(c1) / 1e3 / 10) / 1e9
         del src, dst
 
+        # ---- generic compressed-row gather-scatter (sem_gs) over this box's
+        # global ids g = I + (nx N + 1)(J + (ny N + 1) K), built on the host
+        ee = np.arange(nx * ny * nz)
+        ll = np.arange(N + 1)
+        gI = ((ee % nx) * N)[:, None, None, None] + ll[None, None, None, :]
+        gJ = (((ee // nx) % ny) * N)[:, None, None, None] + ll[None, None, :, None]
+        gK = ((ee // (nx * ny)) * N)[:, None, None, None] + ll[None, :, None, None]
+        gid = (gI + (nx * N + 1) * (gJ + (ny * N + 1) * gK)).reshape(-1)
+        del gI, gJ, gK
+        g_off, g_ids = sem.gs_csr_build(gid)
+        del gid
+        g_rows, g_copies = g_off.numel() - 1, g_ids.numel()
+        g_off, g_ids = g_off.to(dev), g_ids.to(dev)
+        wg = w.clone()
+        sem.gs(g_off, g_ids, wg)
+        c0.record(stream)
+        for _ in range(args.ax_reps):
+            sem.gs(g_off, g_ids, wg)
+        c1.record(stream)
+        torch.cuda.synchronize()
+        gs_s = c0.elapsed_time(c1) / 1e3 / args.ax_reps
+        # algorithmic bytes: each copy read and written (16 B) plus its id (4 B); offsets (4 B/row)
+        gs_bytes = 20.0 * g_copies + 4.0 * (g_rows + 1)
+        gs_info = {"rows": g_rows, "copies": g_copies, "us": gs_s * 1e6,
+                   "algorithmic_bytes": gs_bytes, "gbs": gs_bytes / gs_s / 1e9}
+        print(f"[bench] gs_csr: {gs_info}", file=sys.stderr, flush=True)
+        del g_off, g_ids, wg
+
         # ---- precision form: inner-outer CG with the FP32 / BF16 operator
         mixed = {}
         x64 = x.clone()
@@ -526,6 +554,7 @@ def main(argv=None) -> int:
         "stream_gbs_measured": stream_gbs,
         "ax_frac_of_measured_stream": achieved / stream_gbs,
         "ax_masked_gdofs": gdof / axm_s / 1e9,
+        "gs_csr": gs_info,
         "roofline": {
             "kernel": "ax_mfma_kernel<8, PrecF64, false> (sem_ax element operator, N=7: the "
                       "matrix-core tile, the library default at this order)",

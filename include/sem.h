@@ -176,6 +176,34 @@ size_t vec_dot_workspace_bytes(int64_t n);
 int vec_dot(int64_t n, const double *x_dev, const double *y_dev, const double *wt_dev,
             double *out_dev, void *dev_ws, size_t ws_bytes, void *stream);
 
+/* Generic gather-scatter (the "gs" kernel of paper Sec. V-B: a loop over the
+ * unique ids of shared nodes, and for each an inner loop over its copies) for
+ * any map of L-vector entries to global ids, e.g. a periodic box or an
+ * unstructured mesh.  The box mesh's sem_ax and sem_cg do not need it.
+ *
+ * sem_gs_csr_build (host only, synchronous, no HIP call) turns n global ids
+ * gid_host[0..n-1] (each in [0, 2^31-1], n <= 2^31-1, host memory) into
+ * compressed rows: one row per id that occurs at least twice, rows in
+ * ascending id order, a row's copies (L indices) in ascending order.
+ * Row r's copies are ids_host[offsets_host[r] .. offsets_host[r+1]-1].
+ * With offsets_host = ids_host = NULL it only sets *n_rows and *n_copies;
+ * otherwise offsets_host holds offsets_cap >= *n_rows + 1 entries and
+ * ids_host ids_cap >= *n_copies entries (else SEM_ERR_NOMEM).  All buffers
+ * belong to the caller. */
+int sem_gs_csr_build(int64_t n, const int64_t *gid_host, int32_t *offsets_host, int64_t offsets_cap,
+                     int32_t *ids_host, int64_t ids_cap, int32_t *n_rows, int64_t *n_copies);
+
+/* w <- Q Q^T w over the rows: every copy of a row receives the sum of the
+ * row's copies, added in row order starting from 0 in FP64; entries in no
+ * row are unchanged.  offsets_dev (n_rows + 1 int32) and ids_dev are device
+ * copies of what sem_gs_csr_build produced; w_dev holds n doubles.  Rows must
+ * be disjoint (as built): rows sharing an entry race.  An id outside [0, n)
+ * is skipped, never dereferenced.  Asynchronous on stream; the result is
+ * bitwise independent of the launch. */
+int sem_gs(int32_t n_rows, const int32_t *offsets_dev, const int32_t *ids_dev, int64_t n,
+           double *w_dev, void *stream);
+
+
 /* Copy a setup field (enum sem_field) into dst_dev, which must hold the size
  * listed with the field. */
 int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);

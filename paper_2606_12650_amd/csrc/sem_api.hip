@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "sem_device.h"
+#include "sem_gs.h"
 #include "sem_internal.h"
 
 using semk::Box;
@@ -532,6 +533,25 @@ int vec_axpy(int64_t n, double alpha, const double *x, double *y, void *stream) 
   if (n < 0) return fail(SEM_ERR_ARG, "vec_axpy: n < 0");
   if (n > 0 && (!x || !y)) return fail(SEM_ERR_ARG, "vec_axpy: null vector");
   SEM_HIP(semk::launch_axpy(n, alpha, x, y, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+int sem_gs_csr_build(int64_t n, const int64_t *gid, int32_t *offsets, int64_t offsets_cap,
+                     int32_t *ids, int64_t ids_cap, int32_t *n_rows, int64_t *n_copies) {
+  if (n < 0 || n > INT32_MAX) return fail(SEM_ERR_ARG, "sem_gs_csr_build: n must be in [0, 2^31-1]");
+  if (n > 0 && !gid) return fail(SEM_ERR_ARG, "sem_gs_csr_build: null id array");
+  if (!n_rows || !n_copies) return fail(SEM_ERR_ARG, "sem_gs_csr_build: null size output");
+  const char *why = "";
+  const int rc = semk::build_gs_csr(n, gid, offsets, offsets_cap, ids, ids_cap, n_rows, n_copies, &why);
+  return rc == SEM_OK ? SEM_OK : fail(rc, why);
+}
+
+int sem_gs(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n, double *w,
+           void *stream) {
+  if (n_rows < 0) return fail(SEM_ERR_ARG, "sem_gs: n_rows < 0");
+  if (n < 0) return fail(SEM_ERR_ARG, "sem_gs: n < 0");
+  if (n_rows > 0 && (!offsets || !ids || !w)) return fail(SEM_ERR_ARG, "sem_gs: null pointer");
+  SEM_HIP(semk::launch_gs_rows(n_rows, offsets, ids, n, w, (hipStream_t)stream));
   return SEM_OK;
 }
 

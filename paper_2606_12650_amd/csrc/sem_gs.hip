@@ -1,0 +1,138 @@
+// Generic gather-scatter on gfx950: the "gs" kernel of paper Sec. V-B in its
+// own form, a loop over the unique ids of shared nodes with an inner loop over
+// each id's copies, for any map of L-vector entries to global ids (periodic
+// boxes, unstructured meshes).  The box mesh's CG does not use it: there the
+// summation is fused into the operator and update kernels by index arithmetic.
+//
+// Layout (compressed rows, built once on the host):
+//   offsets[r] .. offsets[r+1]-1  positions in ids of row r's copies
+//   ids[q]                        an L-vector index
+// Rows hold only ids with two or more copies, ascending id; a row's copies are
+// in ascending L-index order, so consecutive rows of a box-like numbering
+// touch neighbouring nodes and the loads of a wave fall on few cache lines.
+//
+// Kernel: one thread per row.  The row's copies are loaded, summed in row
+// order from 0 in FP64 and the sum is stored back to each copy.  Rows are
+// disjoint, so no two threads touch one entry and no atomics are needed; the
+// sum order is fixed, so the result does not depend on the launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "sem_gs.h"
+#include "sem_internal.h"
+
+namespace semk {
+
+namespace {
+
+constexpr int kGsThreads = 256;
+// Copies a thread keeps in registers between the sum and the stores; longer
+// rows (more than 8 copies cannot occur on a conforming hexahedral mesh) take
+// a second pass over the vector.
+constexpr int kGsRegCopies = 8;
+
+__global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
+                                                             const int32_t *__restrict__ offsets,
+                                                             const int32_t *__restrict__ ids,
+                                                             int64_t n, double *__restrict__ w) {
+  const int64_t r = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
+  if (r >= n_rows) return;
+  const int32_t a = offsets[r];
+  const int32_t b = offsets[r + 1];
+  const int32_t len = b - a;
+  if (len <= kGsRegCopies) {
+    int32_t idx[kGsRegCopies];
+    double val[kGsRegCopies];
+#pragma unroll
+    for (int q = 0; q < kGsRegCopies; ++q) {
+      idx[q] = q < len ? ids[a + q] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kGsRegCopies; ++q) {
+      val[q] = (idx[q] >= 0 && idx[q] < n) ? w[idx[q]] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGsRegCopies; ++q)
+      if (q < len) s += val[q];
+#pragma unroll
+    for (int q = 0; q < kGsRegCopies; ++q)
+      if (idx[q] >= 0 && idx[q] < n) w[idx[q]] = s;
+    return;
+  }
+  double s = 0.0;
+  for (int32_t q = a; q < b; ++q) {
+    const int32_t i = ids[q];
+    if (i >= 0 && i < n) s += w[i];
+  }
+  for (int32_t q = a; q < b; ++q) {
+    const int32_t i = ids[q];
+    if (i >= 0 && i < n) w[i] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gs_rows(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n,
+                          double *w, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n_rows + kGsThreads - 1) / kGsThreads);
+  hipLaunchKernelGGL(gs_rows_kernel, dim3(blocks), dim3(kGsThreads), 0, s, n_rows, offsets, ids,
+                     n, w);
+  return hipGetLastError();
+}
+
+int build_gs_csr(int64_t n, const int64_t *gid, int32_t *offsets, int64_t offsets_cap,
+                 int32_t *ids, int64_t ids_cap, int32_t *n_rows, int64_t *n_copies,
+                 const char **why) {
+  // Sort keys (id, L index): ascending id, and within an id ascending L index.
+  std::vector<uint64_t> key((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (gid[i] < 0 || gid[i] > INT32_MAX) {
+      *why = "sem_gs_csr_build: a global id is negative or above 2^31-1";
+      return SEM_ERR_ARG;
+    }
+    key[(size_t)i] = ((uint64_t)gid[i] << 32) | (uint64_t)i;
+  }
+  std::sort(key.begin(), key.end());
+  int64_t rows = 0, copies = 0;
+  for (int64_t q = 0; q < n;) {
+    const uint64_t g = key[(size_t)q] >> 32;
+    int64_t end = q + 1;
+    while (end < n && (key[(size_t)end] >> 32) == g) ++end;
+    if (end - q >= 2) {
+      ++rows;
+      copies += end - q;
+    }
+    q = end;
+  }
+  *n_rows = (int32_t)rows;
+  *n_copies = copies;
+  if (!offsets && !ids) return SEM_OK;  // size query
+  if (!offsets || !ids) {
+    *why = "sem_gs_csr_build: offsets and ids must both be given or both be NULL";
+    return SEM_ERR_ARG;
+  }
+  if (offsets_cap < rows + 1 || ids_cap < copies) {
+    *why = "sem_gs_csr_build: output capacity below the sizes of the rows";
+    return SEM_ERR_NOMEM;
+  }
+  int64_t r = 0, c = 0;
+  offsets[0] = 0;
+  for (int64_t q = 0; q < n;) {
+    const uint64_t g = key[(size_t)q] >> 32;
+    int64_t end = q + 1;
+    while (end < n && (key[(size_t)end] >> 32) == g) ++end;
+    if (end - q >= 2) {
+      for (int64_t t = q; t < end; ++t) ids[c++] = (int32_t)(key[(size_t)t] & 0xffffffffu);
+      offsets[++r] = (int32_t)c;
+    }
+    q = end;
+  }
+  return SEM_OK;
+}
+
+}  // namespace semk

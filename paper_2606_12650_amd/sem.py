@@ -158,6 +158,40 @@ def vec_axpy(alpha: float, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
     return y
 
 
+def gs_csr_build(gid) -> tuple[torch.Tensor, torch.Tensor]:
+    """``sem_gs_csr_build``: compressed rows (offsets, ids; int32 CPU tensors)
+    of the ids in ``gid`` (host int64 array or tensor) that occur at least
+    twice."""
+    g = torch.as_tensor(gid, dtype=torch.int64).reshape(-1).contiguous().cpu()
+    n = g.numel()
+    rows, copies = ctypes.c_int32(0), ctypes.c_int64(0)
+    lib = L.lib()
+    L.check("sem_gs_csr_build", lib.sem_gs_csr_build(n, _ptr(g), None, 0, None, 0,
+                                                     ctypes.byref(rows), ctypes.byref(copies)))
+    offsets = torch.empty(rows.value + 1, dtype=torch.int32)
+    ids = torch.empty(max(copies.value, 1), dtype=torch.int32)
+    L.check("sem_gs_csr_build", lib.sem_gs_csr_build(n, _ptr(g), _ptr(offsets), offsets.numel(),
+                                                     _ptr(ids), ids.numel(), ctypes.byref(rows),
+                                                     ctypes.byref(copies)))
+    return offsets, ids[:copies.value]
+
+
+def gs(offsets: torch.Tensor, ids: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+    """``sem_gs``: in place, every copy of a row of (offsets, ids) receives the
+    sum of the row's copies.  offsets and ids are int32 tensors on w's device."""
+    n = w.numel()
+    _check_vec(w, n, "w", w.device)
+    for t, name in ((offsets, "offsets"), (ids, "ids")):
+        if t.dtype != torch.int32 or t.device != w.device or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous int32 tensor on {w.device}")
+    n_rows = offsets.numel() - 1
+    if n_rows < 0:
+        raise ValueError("offsets must hold n_rows + 1 entries")
+    L.check("sem_gs", L.lib().sem_gs(n_rows, _ptr(offsets), _ptr(ids), n, _ptr(w),
+                                     _stream(w.device)))
+    return w
+
+
 def vec_dot_workspace(n: int, device) -> torch.Tensor:
     nbytes = int(L.lib().vec_dot_workspace_bytes(int(n)))
     return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
