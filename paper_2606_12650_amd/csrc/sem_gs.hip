@@ -11,7 +11,7 @@
 // in ascending L-index order, so consecutive rows of a box-like numbering
 // touch neighbouring nodes and the loads of a wave fall on few cache lines.
 //
-// Kernel: one thread per row.  The row's copies are loaded, summed in row
+// Kernel: two rows per thread.  A row's copies are loaded, summed in row
 // order from 0 in FP64 and the sum is stored back to each copy.  Rows are
 // disjoint, so no two threads touch one entry and no atomics are needed; the
 // sum order is fixed, so the result does not depend on the launch.
@@ -33,44 +33,63 @@ constexpr int kGsThreads = 256;
 // rows (more than 8 copies cannot occur on a conforming hexahedral mesh) take
 // a second pass over the vector.
 constexpr int kGsRegCopies = 8;
+// Rows per thread.  Each thread's work is the dependent chain offsets -> ids
+// -> w -> store; giving a thread two rows whose loads are issued together
+// doubles the loads in flight per wave at the same occupancy.
+constexpr int kGsRowsPerThread = 2;
 
+// Rows of work-group b: b*R*256 + t + 256*k for thread t and k < R, so each
+// load instruction of a wave touches 64 consecutive rows.
+template <int R>
 __global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
                                                              const int32_t *__restrict__ offsets,
                                                              const int32_t *__restrict__ ids,
                                                              int64_t n, double *__restrict__ w) {
-  const int64_t r = (int64_t)blockIdx.x * kGsThreads + threadIdx.x;
-  if (r >= n_rows) return;
-  const int32_t a = offsets[r];
-  const int32_t b = offsets[r + 1];
-  const int32_t len = b - a;
-  if (len <= kGsRegCopies) {
-    int32_t idx[kGsRegCopies];
-    double val[kGsRegCopies];
+  const int64_t base = (int64_t)blockIdx.x * (kGsThreads * R) + threadIdx.x;
+  int32_t a[R], len[R];
 #pragma unroll
-    for (int q = 0; q < kGsRegCopies; ++q) {
-      idx[q] = q < len ? ids[a + q] : -1;
+  for (int k = 0; k < R; ++k) {
+    const int64_t r = base + (int64_t)k * kGsThreads;
+    a[k] = 0;
+    len[k] = 0;
+    if (r < n_rows) {
+      a[k] = offsets[r];
+      len[k] = offsets[r + 1] - a[k];
     }
+  }
+  int32_t idx[R][kGsRegCopies];
 #pragma unroll
-    for (int q = 0; q < kGsRegCopies; ++q) {
-      val[q] = (idx[q] >= 0 && idx[q] < n) ? w[idx[q]] : 0.0;
-    }
-    double s = 0.0;
+  for (int k = 0; k < R; ++k)
 #pragma unroll
     for (int q = 0; q < kGsRegCopies; ++q)
-      if (q < len) s += val[q];
+      idx[k][q] = (q < len[k] && len[k] <= kGsRegCopies) ? ids[a[k] + q] : -1;
+  double val[R][kGsRegCopies];
+#pragma unroll
+  for (int k = 0; k < R; ++k)
 #pragma unroll
     for (int q = 0; q < kGsRegCopies; ++q)
-      if (idx[q] >= 0 && idx[q] < n) w[idx[q]] = s;
-    return;
-  }
-  double s = 0.0;
-  for (int32_t q = a; q < b; ++q) {
-    const int32_t i = ids[q];
-    if (i >= 0 && i < n) s += w[i];
-  }
-  for (int32_t q = a; q < b; ++q) {
-    const int32_t i = ids[q];
-    if (i >= 0 && i < n) w[i] = s;
+      val[k][q] = (idx[k][q] >= 0 && idx[k][q] < n) ? w[idx[k][q]] : 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    if (len[k] <= kGsRegCopies) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGsRegCopies; ++q)
+        if (q < len[k]) s += val[k][q];
+#pragma unroll
+      for (int q = 0; q < kGsRegCopies; ++q)
+        if (idx[k][q] >= 0 && idx[k][q] < n) w[idx[k][q]] = s;
+    } else {
+      double s = 0.0;
+      for (int32_t q = a[k]; q < a[k] + len[k]; ++q) {
+        const int32_t i = ids[q];
+        if (i >= 0 && i < n) s += w[i];
+      }
+      for (int32_t q = a[k]; q < a[k] + len[k]; ++q) {
+        const int32_t i = ids[q];
+        if (i >= 0 && i < n) w[i] = s;
+      }
+    }
   }
 }
 
@@ -79,9 +98,10 @@ __global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
 hipError_t launch_gs_rows(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n,
                           double *w, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((n_rows + kGsThreads - 1) / kGsThreads);
-  hipLaunchKernelGGL(gs_rows_kernel, dim3(blocks), dim3(kGsThreads), 0, s, n_rows, offsets, ids,
-                     n, w);
+  constexpr int per_block = kGsThreads * kGsRowsPerThread;
+  const unsigned blocks = (unsigned)((n_rows + per_block - 1) / per_block);
+  hipLaunchKernelGGL(gs_rows_kernel<kGsRowsPerThread>, dim3(blocks), dim3(kGsThreads), 0, s,
+                     n_rows, offsets, ids, n, w);
   return hipGetLastError();
 }
 
