@@ -189,7 +189,8 @@ int vec_dot(int64_t n, const double *x_dev, const double *y_dev, const double *w
  * With offsets_host = ids_host = NULL it only sets *n_rows and *n_copies;
  * otherwise offsets_host holds offsets_cap >= *n_rows + 1 entries and
  * ids_host ids_cap >= *n_copies entries (else SEM_ERR_NOMEM).  All buffers
- * belong to the caller. */
+ * belong to the caller.  The sort takes 8 bytes of host memory per entry;
+ * if that allocation fails the call returns SEM_ERR_NOMEM. */
 int sem_gs_csr_build(int64_t n, const int64_t *gid_host, int32_t *offsets_host, int64_t offsets_cap,
                      int32_t *ids_host, int64_t ids_cap, int32_t *n_rows, int64_t *n_copies);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -542,7 +543,12 @@ int sem_gs_csr_build(int64_t n, const int64_t *gid, int32_t *offsets, int64_t of
   if (n > 0 && !gid) return fail(SEM_ERR_ARG, "sem_gs_csr_build: null id array");
   if (!n_rows || !n_copies) return fail(SEM_ERR_ARG, "sem_gs_csr_build: null size output");
   const char *why = "";
-  const int rc = semk::build_gs_csr(n, gid, offsets, offsets_cap, ids, ids_cap, n_rows, n_copies, &why);
+  int rc;
+  try {
+    rc = semk::build_gs_csr(n, gid, offsets, offsets_cap, ids, ids_cap, n_rows, n_copies, &why);
+  } catch (const std::bad_alloc &) {
+    return fail(SEM_ERR_NOMEM, "sem_gs_csr_build: out of host memory for the sort keys");
+  }
   return rc == SEM_OK ? SEM_OK : fail(rc, why);
 }
 
