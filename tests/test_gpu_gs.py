@@ -85,3 +85,38 @@ def test_gs_full_size_box_bitwise():
     out, off, ids = _run(gid, v)
     assert off.size - 1 == int((np.bincount(gid) >= 2).sum())
     assert np.array_equal(out, op.dssum_fast(v, gid))
+
+
+@pytest.mark.parametrize("amp", [0.0, 0.05])
+def test_periodic_operator_from_local_operator_and_gs(amp):
+    """A mesh the box index arithmetic cannot assemble: the fully periodic box
+    (the deformation vanishes on the box faces, so the geometry is periodic
+    too).  sem_ax(LOCAL) followed by sem_gs over the periodic ids against the
+    oracle's element operator and row loop, and the symmetry of the result in
+    the multiplicity-weighted inner product for continuous periodic u, v."""
+    nx, ny, nz, N = 3, 2, 4, 5
+    gid = ogs.periodic_global_ids(nx, ny, nz, N)
+    pr = op.Problem(nx, ny, nz, N, amp)
+    A = sem.SemOperator(nx, ny, nz, N, amp, device=DEV)
+    off, ids = sem.gs_csr_build(gid)
+    off_d, ids_d = off.to(DEV), ids.to(DEV)
+    rng = np.random.default_rng(31)
+    nu = int(gid.max()) + 1
+    u, v = rng.uniform(-1, 1, nu)[gid], rng.uniform(-1, 1, nu)[gid]
+    outs = []
+    for x in (u, v):
+        w = A.ax(torch.from_numpy(x).to(DEV), sem.LOCAL)
+        sem.gs(off_d, ids_d, w)
+        torch.cuda.synchronize()
+        outs.append(w.cpu().numpy())
+    ref_u = ogs.gs_csr(pr.ax_local(u).reshape(-1), off.numpy(), ids.numpy())
+    assert np.max(np.abs(outs[0] - ref_u)) <= 1e-12 * np.max(np.abs(ref_u))
+    c = 1.0 / op.multiplicity(gid)
+    a, b = np.sum(c * u * outs[1]), np.sum(c * v * outs[0])
+    assert abs(a - b) <= 1e-12 * np.sum(np.abs(c * u * outs[1]))
+    # constants are in the null space of the periodic operator
+    w1 = A.ax(torch.ones(A.L, dtype=torch.float64, device=DEV), sem.LOCAL)
+    sem.gs(off_d, ids_d, w1)
+    torch.cuda.synchronize()
+    assert np.max(np.abs(w1.cpu().numpy())) <= 1e-12 * np.max(np.abs(outs[0]))
+    A.close()
