@@ -100,3 +100,33 @@ def test_periodic_gs_of_continuous_periodic_field():
     u = vals[g]  # continuous on the periodic lattice
     off, ids = gs.csr_from_ids(g)
     np.testing.assert_allclose(gs.gs_csr(u, off, ids), op.multiplicity(g) * u, rtol=1e-15)
+
+
+def _gs_mutant(kind):
+    """Plausible mistakes in the row loop of the gather-scatter."""
+    def f(v, offsets, ids):
+        out = np.array(v, dtype=np.float64, copy=True)
+        for r in range(len(offsets) - 1):
+            members = ids[offsets[r]:offsets[r + 1]]
+            if kind == "drop_last":
+                s = float(np.sum(v[members[:-1]]))
+            elif kind == "off_by_one":
+                s = float(np.sum(v[ids[offsets[r]:offsets[r + 1] - 1]])) + v[members[0]]
+            else:  # "first_only": the sum is written to the first copy only
+                s = float(np.sum(v[members]))
+                out[members[0]] = s
+                continue
+            out[members] = s
+        return out
+    return f
+
+
+@pytest.mark.parametrize("kind", ["drop_last", "off_by_one", "first_only"])
+def test_planted_gs_mistakes_are_caught(kind):
+    rng = np.random.default_rng(5)
+    gid = rng.integers(0, 60, 200)
+    v = rng.uniform(-1, 1, 200)
+    off, ids = gs.csr_from_ids(gid)
+    Q = dense_q(gid)
+    out = _gs_mutant(kind)(v, off, ids)
+    assert np.max(np.abs(out - Q @ (Q.T @ v))) > 1e-12
