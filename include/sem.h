@@ -75,7 +75,10 @@ typedef struct sem_ctx sem_ctx;  /* opaque host-side handle */
 
 typedef struct {
   int32_t nelx, nely, nelz; /* elements per direction, each >= 1               */
-  int32_t order;            /* polynomial order N, 1..12                        */
+  int32_t order;            /* polynomial order N: 1..12 (kernels built with the
+                               library), 13..15 (kernels compiled at set-up
+                               for the device, FP64 and the matrix-core tile
+                               only); else SEM_ERR_UNSUPPORTED                 */
   double deform_amp;        /* 0 = affine elements                              */
   int32_t lowprec;          /* SEM_F64 (none), SEM_F32 or SEM_BF16: also keep a
                                rounded copy of G for the inner solver of the
@@ -95,19 +98,40 @@ typedef struct {
 
 enum { SEM_FLAG_MFMA = 1, SEM_FLAG_VALU = 2 };
 
-/* Device bytes sem_setup needs for this mesh (0 if the descriptor is invalid).
- * It covers G, the Jacobi diagonal, D, the CG vectors and reduction scratch;
- * it is the footprint a scheduler can admit a solve by. */
+/* Device bytes sem_setup needs for this mesh (0 if the descriptor is invalid
+ * or unsupported): the problem data of Sec. VIII-A (G, the Jacobi diagonal,
+ * D) plus the CG vectors and reduction scratch.  It is the footprint a
+ * scheduler admits a solve by.  Host only. */
 size_t sem_workspace_bytes(const sem_mesh_desc *desc);
 
-/* Build the operator of `desc` in the caller's workspace: GLL nodes and D on
+/* Build the operator of `desc` in the caller's workspace (the set-up of the
+ * Poisson problem, Sec. VIII-A: a box of E hexahedra with (N+1)^3 nodes each;
+ * the derivative matrices that depend on N, Sec. III): GLL nodes and D on
  * the host, then on the GPU the mesh coordinates, the isoparametric metric G,
  * the Jacobi diagonal (summed over copies) and its inverse.  `dev_ws` must be
  * 256-byte aligned and hold sem_workspace_bytes(desc) bytes.  Synchronous:
- * returns after the stream has finished the setup.  On success *out is a new
- * handle (free with sem_destroy); the workspace belongs to it until then. */
+ * returns after the stream has finished the setup.  For orders 13..15 the
+ * per-order kernels are first compiled for the current device with hipRTC
+ * (N a compile-time constant, as in the built kernels: the jit clause of
+ * Sec. IV), or taken from the process's cache or the disk cache
+ * ($SEM_RTC_CACHE, else $XDG_CACHE_HOME/libsem or $HOME/.cache/libsem); a
+ * compile failure returns SEM_ERR_HIP with the compiler log in
+ * sem_last_error().  Errors: SEM_ERR_ARG (malformed descriptor, null or
+ * misaligned workspace), SEM_ERR_UNSUPPORTED (order or precision outside
+ * what the kernels serve), SEM_ERR_NOMEM (workspace too small), SEM_ERR_HIP.
+ * On success *out is a new handle (free with sem_destroy); the workspace
+ * belongs to it until then. */
 int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *stream,
               sem_ctx **out);
+
+/* Compile and cache, without a GPU, the per-order kernels of an order in
+ * 13..15 for the architecture `arch` ("gfx950", optionally with a feature
+ * suffix such as ":sramecc+:xnack-"), as sem_setup does on first use of
+ * that order; *code_bytes (may be NULL) receives the code object's size.
+ * SEM_ERR_UNSUPPORTED for orders 1..12 (built with the library), above 15
+ * and for any other architecture; SEM_ERR_HIP with the compiler log on a
+ * compile failure. */
+int sem_rtc_build(int order, const char *arch, size_t *code_bytes);
 
 /* Free the host handle (and any captured CG graph).  Never frees dev_ws. */
 int sem_destroy(sem_ctx *ctx);
@@ -143,8 +167,13 @@ typedef struct {
   double inner_rtol;   /* mixed: inner relative tolerance (<=0: 1e-3 for SEM_F32,
                           1e-2 for SEM_BF16)                                   */
   int32_t inner_max;   /* mixed: inner iteration cap per outer step (<=0: 5000) */
-  int32_t reserved;
+  int32_t precond;     /* SEM_PRECOND_JACOBI (0): z = Minv r with the inverse
+                          diagonal of A.  SEM_PRECOND_NONE (1): plain CG, z = r
+                          (the unpreconditioned CG of Sec. VIII-A); FP64 only
+                          (SEM_ERR_ARG with mixed, and in batches)            */
 } sem_cg_opts;
+
+enum { SEM_PRECOND_JACOBI = 0, SEM_PRECOND_NONE = 1 };
 
 typedef struct {
   int32_t iters;        /* CG iterations (mixed: total inner iterations)       */
@@ -154,7 +183,7 @@ typedef struct {
   double rel_res;       /* final ||r||_c/||b||_c (recursive; mixed: true FP64) */
 } sem_cg_info;
 
-/* Jacobi-PCG for A x = b (Sec. VIII-A) with x_0 = 0, c-weighted dots
+/* Jacobi-PCG (or plain CG, opts->precond) for A x = b (Sec. VIII-A) with x_0 = 0, c-weighted dots
  * <x,y>_c = sum_i x_i y_i / mult_i, scalars kept on the device.  b and x are
  * L-vectors (b continuous; boundary entries are ignored), x is overwritten.
  * Blocking: returns when the solve has finished; polls one small status word
@@ -196,13 +225,15 @@ int sem_gs_csr_build(int64_t n, const int64_t *gid_host, int32_t *offsets_host, 
 
 /* w <- Q Q^T w over the rows: every copy of a row receives the sum of the
  * row's copies, added in row order starting from 0 in FP64; entries in no
- * row are unchanged.  offsets_dev (n_rows + 1 int32) and ids_dev are device
- * copies of what sem_gs_csr_build produced; w_dev holds n doubles.  Rows must
- * be disjoint (as built): rows sharing an entry race.  An id outside [0, n)
- * is skipped, never dereferenced.  Asynchronous on stream; the result is
- * bitwise independent of the launch. */
-int sem_gs(int32_t n_rows, const int32_t *offsets_dev, const int32_t *ids_dev, int64_t n,
-           double *w_dev, void *stream);
+ * row are unchanged.  offsets_dev (n_rows + 1 int32) and ids_dev (n_copies
+ * int32, n_copies = offsets[n_rows]) are device copies of what
+ * sem_gs_csr_build produced; w_dev holds n doubles.  Rows must be disjoint
+ * (as built): rows sharing an entry race.  Bad input is skipped, never
+ * dereferenced: a row whose offsets fall outside [0, n_copies] (or decrease)
+ * is left alone, and an id outside [0, n) is ignored.  Asynchronous on
+ * stream; the result is bitwise independent of the launch. */
+int sem_gs(int32_t n_rows, const int32_t *offsets_dev, const int32_t *ids_dev, int64_t n_copies,
+           int64_t n, double *w_dev, void *stream);
 
 
 /* Copy a setup field (enum sem_field) into dst_dev, which must hold the size

@@ -23,6 +23,7 @@ SEM_F64, SEM_F32, SEM_BF16 = 0, 1, 2
 SEM_AX_LOCAL, SEM_AX_ASSEMBLED, SEM_AX_MASKED = 0, 1, 3
 SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2, 3, 4
 SEM_FLAG_MFMA, SEM_FLAG_VALU = 1, 2
+SEM_PRECOND_JACOBI, SEM_PRECOND_NONE = 0, 1
 
 # Every symbol include/sem.h declares.
 EXPORTS = (
@@ -30,7 +31,7 @@ EXPORTS = (
     "vec_axpy", "vec_dot_workspace_bytes", "vec_dot", "sem_export", "sem_last_error",
     "sem_ax_lowp", "sem_batch_workspace_bytes", "sem_batch_create", "sem_batch_set_tile",
     "sem_batch_add", "sem_batch_step", "sem_batch_poll", "sem_batch_remove", "sem_batch_destroy",
-    "sem_gs_csr_build", "sem_gs",
+    "sem_gs_csr_build", "sem_gs", "sem_rtc_build",
 )
 
 
@@ -44,7 +45,7 @@ class SemCgOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("fixed_iter", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-                ("inner_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("inner_max", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class SemCgInfo(ctypes.Structure):
@@ -88,7 +89,8 @@ def _declare(lib):
         "sem_batch_remove": (ctypes.c_int, [vp, ctypes.c_int, vp]),
         "sem_batch_destroy": (ctypes.c_int, [vp]),
         "sem_gs_csr_build": (ctypes.c_int, [i64, vp, vp, i64, vp, i64, P(i32), P(i64)]),
-        "sem_gs": (ctypes.c_int, [i32, vp, vp, i64, vp, vp]),
+        "sem_gs": (ctypes.c_int, [i32, vp, vp, i64, i64, vp, vp]),
+        "sem_rtc_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, P(sz)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

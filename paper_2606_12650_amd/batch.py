@@ -15,7 +15,7 @@ import math
 import torch
 
 from . import _lib as L
-from .sem import CgResult, SemOperator, _ptr, _stream
+from .sem import CgResult, SemOperator, _check_vec, _ptr, _stream
 
 VEC_TILE = 2048  # entries per streaming item
 _PREC_CODE = {"f64": L.SEM_F64, "f32": L.SEM_F32, "bf16": L.SEM_BF16}
@@ -78,6 +78,8 @@ class SemBatch:
             mixed: bool = False, max_iter: int = 0, inner_rtol: float = 0.0, inner_max: int = 0) -> int:
         """Start a solve in a free slot; returns the slot index."""
         x = op.empty() if x is None else x
+        _check_vec(b, op.L, "b", op.device)
+        _check_vec(x, op.L, "x", op.device)
         opts = L.SemCgOpts(float(rtol), int(max_iter), 0, int(bool(mixed)), 0, float(inner_rtol),
                            int(inner_max), 0)
         slot = ctypes.c_int(-1)

@@ -11,8 +11,10 @@
 #include <vector>
 
 #include "sem_device.h"
+#include "sem_error.h"
 #include "sem_gs.h"
 #include "sem_internal.h"
+#include "sem_rtc.h"
 
 using semk::Box;
 using semk::CgState;
@@ -52,25 +54,34 @@ struct Layout {
   size_t total;
 };
 
-bool desc_valid(const sem_mesh_desc *d, std::string *why) {
-  if (!d) { *why = "null mesh descriptor"; return false; }
-  if (d->nelx < 1 || d->nely < 1 || d->nelz < 1) { *why = "element counts must be >= 1"; return false; }
-  if (d->order < semk::kMinOrder || d->order > semk::kMaxOrder) {
-    *why = "order N must be in [1, 12]";
-    return false;
-  }
+// SEM_OK, or SEM_ERR_ARG for a malformed descriptor, or SEM_ERR_UNSUPPORTED
+// for an order or precision no kernel serves: orders 1..12 are built with the
+// library in every precision and element tile; orders 13..15 are compiled at
+// run time in FP64 with the matrix-core tile.
+int desc_check(const sem_mesh_desc *d, std::string *why) {
+  if (!d) { *why = "null mesh descriptor"; return SEM_ERR_ARG; }
+  if (d->nelx < 1 || d->nely < 1 || d->nelz < 1) { *why = "element counts must be >= 1"; return SEM_ERR_ARG; }
+  if (d->order < semk::kMinOrder) { *why = "order N must be >= 1"; return SEM_ERR_ARG; }
   if (d->lowprec != SEM_F64 && d->lowprec != SEM_F32 && d->lowprec != SEM_BF16) {
     *why = "lowprec must be SEM_F64, SEM_F32 or SEM_BF16";
-    return false;
+    return SEM_ERR_ARG;
   }
   if (d->flags != 0 && d->flags != SEM_FLAG_MFMA && d->flags != SEM_FLAG_VALU) {
     *why = "flags must be 0, SEM_FLAG_MFMA or SEM_FLAG_VALU";
-    return false;
+    return SEM_ERR_ARG;
   }
-  if (!std::isfinite(d->deform_amp)) { *why = "deform_amp must be finite"; return false; }
+  if (!std::isfinite(d->deform_amp)) { *why = "deform_amp must be finite"; return SEM_ERR_ARG; }
+  if (d->order > semk::kMaxRtcOrder) {
+    *why = "order N must be in [1, 15] (1..12 built, 13..15 compiled at run time)";
+    return SEM_ERR_UNSUPPORTED;
+  }
+  if (semk::rtc_order(d->order) && (d->lowprec != SEM_F64 || d->flags == SEM_FLAG_VALU)) {
+    *why = "orders 13..15 run in FP64 on the matrix-core tile only (lowprec SEM_F64, flags 0 or SEM_FLAG_MFMA)";
+    return SEM_ERR_UNSUPPORTED;
+  }
   const double L = (double)d->nelx * d->nely * d->nelz * std::pow(d->order + 1.0, 3);
-  if (L > 4.0e9) { *why = "mesh too large (L > 4e9)"; return false; }
-  return true;
+  if (L > 4.0e9) { *why = "mesh too large (L > 4e9)"; return SEM_ERR_ARG; }
+  return SEM_OK;
 }
 
 Box box_of(const sem_mesh_desc *d) { return Box::make(d->nelx, d->nely, d->nelz, d->order); }
@@ -181,6 +192,11 @@ void deriv_host(int N, const std::vector<double> &xs, std::vector<double> *D) {
 
 }  // namespace
 
+namespace semk {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+int set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+}  // namespace semk
+
 struct sem_ctx {
   sem_mesh_desc desc;
   Box box;
@@ -198,10 +214,13 @@ struct sem_ctx {
   CgState host_state;  // staging for the state upload / status reads
   CgState host_inner;
   int in_batch;  // 1 while the context is a slot of a batch
+  // Minv of the FP64 iterations of the running sem_cg call (null: plain CG)
+  const double *cg_minv;
   // cached graphs: [0] FP64 CG iterations into graph_x, [1] inner iterations
   hipGraphExec_t graph[2];
   hipStream_t graph_stream[2];
   double *graph_x[2];
+  const double *graph_minv[2];
   int graph_iters[2];
 };
 
@@ -214,9 +233,9 @@ namespace {
 // one-group step for beta, the residual and the done flag.
 int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_f64(b, c->desc.flags, c->D, c->G, c->p, c->w, c->r, c->minv, x, c->st, c->part_ax, s));
+  SEM_HIP(semk::launch_ax_f64(b, c->desc.flags, c->D, c->G, c->p, c->w, c->r, c->cg_minv, x, c->st, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
-  SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->minv, c->st, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->cg_minv, c->st, c->part_rr, c->part_rz, s));
   SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_upd_blocks, s));
   return SEM_OK;
 }
@@ -240,6 +259,7 @@ void drop_graph(sem_ctx *c, int slot) {
   c->graph[slot] = nullptr;
   c->graph_stream[slot] = nullptr;
   c->graph_x[slot] = nullptr;
+  c->graph_minv[slot] = nullptr;
   c->graph_iters[slot] = 0;
 }
 
@@ -248,7 +268,7 @@ void drop_graph(sem_ctx *c, int slot) {
 // caller then launches directly), or a negative error.
 int capture_graph(sem_ctx *c, int slot, enqueue_fn fn, double *x, int iters, hipStream_t s) {
   if (c->graph[slot] && c->graph_stream[slot] == s && c->graph_x[slot] == x &&
-      c->graph_iters[slot] == iters)
+      c->graph_minv[slot] == c->cg_minv && c->graph_iters[slot] == iters)
     return SEM_OK;
   drop_graph(c, slot);
   if (s == nullptr) return 1;  // the legacy null stream cannot be captured
@@ -272,6 +292,7 @@ int capture_graph(sem_ctx *c, int slot, enqueue_fn fn, double *x, int iters, hip
   c->graph[slot] = ex;
   c->graph_stream[slot] = s;
   c->graph_x[slot] = x;
+  c->graph_minv[slot] = c->cg_minv;
   c->graph_iters[slot] = iters;
   return SEM_OK;
 }
@@ -309,8 +330,23 @@ const char *sem_last_error(void) { return g_last_error.c_str(); }
 
 size_t sem_workspace_bytes(const sem_mesh_desc *desc) {
   std::string why;
-  if (!desc_valid(desc, &why)) return 0;
+  if (desc_check(desc, &why) != SEM_OK) return 0;
   return layout_of(desc).total;
+}
+
+int sem_rtc_build(int order, const char *arch, size_t *code_bytes) {
+  if (!arch || !*arch) return fail(SEM_ERR_ARG, "sem_rtc_build: null or empty architecture");
+  if (order < semk::kMinOrder) return fail(SEM_ERR_ARG, "sem_rtc_build: order must be >= 1");
+  if (!semk::rtc_order(order))
+    return fail(SEM_ERR_UNSUPPORTED, "sem_rtc_build: orders 13..15 are compiled at run time (1..12 are built)");
+  if (!semk::rtc_arch_supported(arch))
+    return fail(SEM_ERR_UNSUPPORTED, std::string("sem_rtc_build: architecture ") + arch + " is not gfx950");
+  std::string why;
+  size_t bytes = 0;
+  const hipError_t e = semk::rtc_build(order, arch, &bytes, &why);
+  if (e != hipSuccess) return fail(SEM_ERR_HIP, "sem_rtc_build: " + why);
+  if (code_bytes) *code_bytes = bytes;
+  return SEM_OK;
 }
 
 int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *stream,
@@ -318,13 +354,20 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   std::string why;
   if (!out) return fail(SEM_ERR_ARG, "sem_setup: null output handle");
   *out = nullptr;
-  if (!desc_valid(desc, &why)) return fail(SEM_ERR_ARG, "sem_setup: " + why);
+  const int dc = desc_check(desc, &why);
+  if (dc != SEM_OK) return fail(dc, "sem_setup: " + why);
   if (!dev_ws) return fail(SEM_ERR_ARG, "sem_setup: null workspace");
   if (((uintptr_t)dev_ws) % kAlign != 0) return fail(SEM_ERR_ARG, "sem_setup: workspace not 256-byte aligned");
   const Layout lay = layout_of(desc);
   if (ws_bytes < lay.total)
     return fail(SEM_ERR_NOMEM, "sem_setup: workspace has " + std::to_string(ws_bytes) +
                                    " bytes, needs " + std::to_string(lay.total));
+  if (semk::rtc_order(desc->order)) {
+    // kernels of this order: compiled now (or taken from the cache) and loaded
+    std::string rwhy;
+    const hipError_t re = semk::rtc_prepare(desc->order, &rwhy);
+    if (re != hipSuccess) return hip_fail(re, ("sem_setup: run-time kernels: " + rwhy).c_str());
+  }
   hipStream_t s = (hipStream_t)stream;
   sem_ctx *c = new sem_ctx();
   c->desc = *desc;
@@ -352,8 +395,10 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
     c->graph[slot] = nullptr;
     c->graph_stream[slot] = nullptr;
     c->graph_x[slot] = nullptr;
+    c->graph_minv[slot] = nullptr;
     c->graph_iters[slot] = 0;
   }
+  c->cg_minv = c->minv;
   const bool lowp = desc->lowprec != SEM_F64;
   c->Dlo = lowp ? (float *)(c->ws + lay.Dlo) : nullptr;
   c->Glo = lowp ? (void *)(c->ws + lay.Glo) : nullptr;
@@ -447,7 +492,13 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
     return fail(SEM_ERR_ARG, "sem_cg: mixed precision runs in tolerance mode only");
   if (opts->fixed_iter <= 0 && !(opts->rtol > 0.0))
     return fail(SEM_ERR_ARG, "sem_cg: rtol must be > 0 unless fixed_iter > 0");
+  if (opts->precond != SEM_PRECOND_JACOBI && opts->precond != SEM_PRECOND_NONE)
+    return fail(SEM_ERR_ARG, "sem_cg: precond must be SEM_PRECOND_JACOBI or SEM_PRECOND_NONE");
+  if (opts->precond == SEM_PRECOND_NONE && opts->mixed)
+    return fail(SEM_ERR_ARG, "sem_cg: the plain CG (SEM_PRECOND_NONE) runs in FP64 only");
   hipStream_t s = (hipStream_t)stream;
+  // plain CG: a null Minv makes every CG kernel take z = r
+  ctx->cg_minv = opts->precond == SEM_PRECOND_NONE ? nullptr : ctx->minv;
   const int max_iter = opts->fixed_iter > 0 ? opts->fixed_iter : (opts->max_iter > 0 ? opts->max_iter : 20000);
   int every = opts->check_every > 0 ? opts->check_every : 25;
 
@@ -456,7 +507,7 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
   h.max_iter = opts->mixed ? (opts->max_iter > 0 ? opts->max_iter : 50) : max_iter;
   h.rtol2 = opts->fixed_iter > 0 ? -1.0 : opts->rtol * opts->rtol;
   SEM_HIP(hipMemcpyAsync(ctx->st, &h, sizeof(CgState), hipMemcpyHostToDevice, s));
-  SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->minv, ctx->st, ctx->part_rz,
+  SEM_HIP(semk::launch_cg_init(ctx->box, b, x, ctx->r, ctx->p, ctx->cg_minv, ctx->st, ctx->part_rz,
                                ctx->part_rr, s));
   int status = SEM_OK;
   if (!opts->mixed) {
@@ -552,12 +603,13 @@ int sem_gs_csr_build(int64_t n, const int64_t *gid, int32_t *offsets, int64_t of
   return rc == SEM_OK ? SEM_OK : fail(rc, why);
 }
 
-int sem_gs(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n, double *w,
-           void *stream) {
+int sem_gs(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n_copies, int64_t n,
+           double *w, void *stream) {
   if (n_rows < 0) return fail(SEM_ERR_ARG, "sem_gs: n_rows < 0");
   if (n < 0) return fail(SEM_ERR_ARG, "sem_gs: n < 0");
+  if (n_copies < 0 || n_copies > INT32_MAX) return fail(SEM_ERR_ARG, "sem_gs: n_copies must be in [0, 2^31-1]");
   if (n_rows > 0 && (!offsets || !ids || !w)) return fail(SEM_ERR_ARG, "sem_gs: null pointer");
-  SEM_HIP(semk::launch_gs_rows(n_rows, offsets, ids, n, w, (hipStream_t)stream));
+  SEM_HIP(semk::launch_gs_rows(n_rows, offsets, ids, n_copies, n, w, (hipStream_t)stream));
   return SEM_OK;
 }
 
@@ -746,6 +798,8 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   if (ctx->in_batch) return fail(SEM_ERR_ARG, "sem_batch_add: the context is already in a batch");
   if (b == x) return fail(SEM_ERR_ARG, "sem_batch_add: b and x must differ");
   if (opts->fixed_iter > 0) return fail(SEM_ERR_ARG, "sem_batch_add: batches run in tolerance mode");
+  if (opts->precond != SEM_PRECOND_JACOBI)
+    return fail(SEM_ERR_ARG, "sem_batch_add: batches run Jacobi-PCG (precond must be SEM_PRECOND_JACOBI)");
   if (!(opts->rtol > 0.0)) return fail(SEM_ERR_ARG, "sem_batch_add: rtol must be > 0");
   if (opts->mixed && ctx->desc.lowprec == SEM_F64)
     return fail(SEM_ERR_ARG, "sem_batch_add: mixed precision needs a low-precision copy");

@@ -34,7 +34,7 @@
 
 #include "sem_ax_tile.h"
 #include "sem_device.h"
-#include "sem_internal.h"
+#include "sem_types.h"
 
 namespace semk {
 
@@ -238,7 +238,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     pv[m] = ld_once(u + idx[m]);
     if (CG) {
       xv[m] = ld_once(x + idx[m]);
-      mv[m] = ld_once(minv + idx[m]);
+      mv[m] = minv_at(minv, idx[m]);
       rv[m] = ld_once(r + idx[m]);
     }
   }

@@ -5,7 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "sem_internal.h"
+#include "sem_types.h"
 
 namespace semk {
 
@@ -73,6 +73,14 @@ __device__ __forceinline__ int opaque_tid() {
   int t;
   asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
   return t;
+}
+
+// The Jacobi inverse diagonal at idx, or 1 when the solve runs without a
+// preconditioner (minv == nullptr, the plain CG).  Every masked node carries
+// r = 0 throughout a solve, so 1 there gives z = r = mask o r as well.
+template <typename T>
+__device__ __forceinline__ T minv_at(const T *minv, int64_t idx) {
+  return minv ? ld_once(minv + idx) : (T)1;
 }
 
 template <class P>

@@ -44,7 +44,8 @@ template <int R>
 __global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
                                                              const int32_t *__restrict__ offsets,
                                                              const int32_t *__restrict__ ids,
-                                                             int64_t n, double *__restrict__ w) {
+                                                             int64_t n_copies, int64_t n,
+                                                             double *__restrict__ w) {
   const int64_t base = (int64_t)blockIdx.x * (kGsThreads * R) + threadIdx.x;
   int32_t a[R], len[R];
 #pragma unroll
@@ -53,8 +54,12 @@ __global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
     a[k] = 0;
     len[k] = 0;
     if (r < n_rows) {
-      a[k] = offsets[r];
-      len[k] = offsets[r + 1] - a[k];
+      // a row whose copies do not lie inside ids[0 .. n_copies-1] is skipped
+      const int32_t lo = offsets[r], hi = offsets[r + 1];
+      if (lo >= 0 && hi >= lo && (int64_t)hi <= n_copies) {
+        a[k] = lo;
+        len[k] = hi - lo;
+      }
     }
   }
   int32_t idx[R][kGsRegCopies];
@@ -95,13 +100,13 @@ __global__ __launch_bounds__(kGsThreads) void gs_rows_kernel(int32_t n_rows,
 
 }  // namespace
 
-hipError_t launch_gs_rows(int32_t n_rows, const int32_t *offsets, const int32_t *ids, int64_t n,
-                          double *w, hipStream_t s) {
+hipError_t launch_gs_rows(int32_t n_rows, const int32_t *offsets, const int32_t *ids,
+                          int64_t n_copies, int64_t n, double *w, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   constexpr int per_block = kGsThreads * kGsRowsPerThread;
   const unsigned blocks = (unsigned)((n_rows + per_block - 1) / per_block);
   hipLaunchKernelGGL(gs_rows_kernel<kGsRowsPerThread>, dim3(blocks), dim3(kGsThreads), 0, s,
-                     n_rows, offsets, ids, n, w);
+                     n_rows, offsets, ids, n_copies, n, w);
   return hipGetLastError();
 }
 

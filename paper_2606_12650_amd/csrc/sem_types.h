@@ -1,0 +1,223 @@
+// Types and launch-shape rules of libsem that device code sees: mesh and
+// solver state, tile shapes, batch records.  Nothing here names the HIP
+// runtime API, so the run-time compiled kernels (orders outside the
+// compiled set) include it as the built kernels do.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sem.h"
+
+namespace semk {
+
+constexpr int kMinOrder = 1;
+constexpr int kMaxOrder = 12;     // orders whose kernels are built with the library
+constexpr int kMaxRtcOrder = 15;  // orders compiled at run time (one MFMA row block: N + 1 <= 16)
+
+// Unsigned division by a runtime constant d >= 1 as a multiply and shift
+// (Granlund-Montgomery): q = (n * M) >> k with k = 32 + ceil(log2 d) and
+// M = ceil(2^k / d) < 2^33; exact for every n < 2^31.
+struct FastDiv {
+  uint64_t M;
+  uint32_t k;
+  uint32_t d;
+  static FastDiv make(uint32_t d) {
+    uint32_t sh = 0;
+    while ((1ull << sh) < d) ++sh;
+    FastDiv f;
+    f.k = 32 + sh;
+    f.M = ((1ull << f.k) + d - 1) / d;
+    f.d = d;
+    return f;
+  }
+  __host__ __device__ uint32_t div(uint32_t n) const { return (uint32_t)(((uint64_t)n * M) >> k); }
+};
+
+// Box mesh dimensions and polynomial order (fdx, fdy divide by nx, ny).
+struct Box {
+  int nx, ny, nz, N;
+  FastDiv fdx, fdy;
+  static Box make(int nx, int ny, int nz, int N) {
+    Box b;
+    b.nx = nx; b.ny = ny; b.nz = nz; b.N = N;
+    b.fdx = FastDiv::make((uint32_t)nx);
+    b.fdy = FastDiv::make((uint32_t)ny);
+    return b;
+  }
+  __host__ __device__ int n1() const { return N + 1; }
+  __host__ __device__ int64_t E() const { return (int64_t)nx * ny * nz; }
+  __host__ __device__ int64_t np() const { return (int64_t)(N + 1) * (N + 1) * (N + 1); }
+  __host__ __device__ int64_t L() const { return E() * np(); }
+};
+
+// Status of a device-resident CG solve.
+enum CgDone : int { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIter = 3 };
+
+// Scalars of the CG recurrence, kept in device memory so that no iteration
+// needs the host.  `done` is first so that a single aligned load checks it.
+struct CgState {
+  int done;
+  int iter;
+  int max_iter;
+  int done_stage;  // 2 when the last finished iteration updated r (x still owes alpha p)
+  double rho;     // <r, Minv r>_c
+  double alpha;
+  double beta;
+  double pap;     // <p, A p>_c
+  double rnorm2;  // <r, r>_c
+  double bnorm2;  // <b, b>_c
+  double rtol2;   // rtol^2 (< 0: fixed-iteration mode, never converges)
+  double tol2;    // rtol2 * bnorm2
+};
+
+// Launch shapes of the element kernels (shared by host sizing code).
+int ax_elements_per_block(int N);
+int64_t ax_num_blocks(const Box &b);
+constexpr int kVecThreads = 256;
+constexpr int kVecItems = 8;   // entries per thread of the streaming kernels
+constexpr int64_t kVecTile = (int64_t)kVecThreads * kVecItems;
+inline int64_t vec_num_blocks(int64_t n) { return (n + kVecTile - 1) / kVecTile; }
+// Launch size (and partial count) of the element-local streaming kernels:
+// tiles padded to a multiple of the XCD count.
+inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) / 8); }
+
+// Tiles of the CG update (the gather-scatter pulled into r -= alpha w) are
+// element-aligned: upd_ept consecutive elements with upd_ks threads per
+// (i, j) column, over all planes or, at the highest orders, over one of
+// upd_kp plane ranges.  Up to order 7 a tile fills 256 threads; above, it
+// holds two elements in FP64 (up to 512 threads) and one in FP32 (at order
+// 11 with two threads per column rather than two plane ranges).  The FP64
+// update from order 9 up keeps linear streaming tiles of kVecTile entries.
+// All of these choices are what measured faster on MI355X.
+__host__ __device__ constexpr int upd_ks(int n1, bool f64) {
+  return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11 || (!f64 && n1 == 12)) ? 2 : 1);
+}
+__host__ __device__ constexpr int upd_ept(int n1, bool f64) {
+  return n1 >= 9 ? (f64 ? 2 : 1) : kVecThreads / (upd_ks(n1, f64) * n1 * n1);
+}
+__host__ __device__ constexpr int upd_kp(int n1, bool f64) {
+  return (n1 >= 13 || (f64 && n1 == 12)) ? 2 : 1;
+}
+__host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
+inline int64_t upd_num_tiles(const Box &b, bool f64) {
+  const int n1 = b.N + 1;
+  if (upd_linear(n1, f64)) return vec_num_blocks(b.L());
+  const int ept = upd_ept(n1, f64);
+  return (b.E() + ept - 1) / ept * upd_kp(n1, f64);
+}
+// Launch size of the update (a multiple of the XCD count).
+inline int64_t upd_grid_blocks(const Box &b, bool f64) {
+  return 8 * ((upd_num_tiles(b, f64) + 7) / 8);
+}
+// Partials a solve's streaming reductions need room for.
+inline int64_t stream_partials(const Box &b) {
+  int64_t v = vec_grid_blocks(b.L());
+  const int64_t u64 = upd_grid_blocks(b, true), u32 = upd_grid_blocks(b, false);
+  if (u64 > v) v = u64;
+  if (u32 > v) v = u32;
+  return v;
+}
+
+// What the gather kernel writes at a node: the sum of its copies
+// (assembled), the same with box-boundary nodes zeroed (masked), or the
+// Jacobi inverse 1/sum with boundary nodes zeroed (inverse).
+enum GatherMode : int { kGatherAssembled = 0, kGatherMasked = 1, kGatherInverse = 2 };
+
+// ---------------------------------------------------------------- operator
+// Which element tile an operator runs by default, per arithmetic class (0 and
+// 3 FP64, 1 FP32, 2 BF16) and order N: the matrix-core tile (sem_ax_mfma.h)
+// where it measured faster on MI355X than the vector-unit tiles
+// (sem_ax_tile.h) inside the CG, i.e. from N = 7 in FP64 and FP32 and from
+// N = 9 in BF16.
+__host__ __device__ constexpr bool op_uses_mfma(int cls, int N) {
+  return (cls == 0 || cls == 3 || cls == 1) ? N >= 7 : N >= 9;
+}
+
+// Operator implementation request: the default above, or forced.
+enum OpImpl : int { kImplDefault = 0, kImplMfma = 1, kImplValu = 2 };
+
+// ---------------------------------------------------------------- batches
+// Phase of a solve inside a batch (advanced on the device).
+enum SlotPhase : int {
+  kPhaseFp64 = 0,       // FP64 Jacobi-PCG iterations
+  kPhaseFp64Done = 1,   // FP64 solve stopped: the last x += alpha p is pending
+  kPhaseInner = 2,      // inner low-precision PCG iterations
+  kPhaseInnerDone = 3,  // inner solve stopped: x += ||r|| (e + alpha p) pending
+  kPhaseOuterOp = 4,    // FP64 true residual of the corrected x
+  kPhaseRestart = 5,    // inner restart r_in = r / ||r|| pending
+  kPhaseFinished = 6,   // nothing left to do
+};
+
+// One solve of a batch: the operator data of its sem_ctx plus its vectors.
+struct BatchSlot {
+  Box box;
+  int N;
+  int vtiles;  // streaming tiles (vec_num_blocks(L)); partials of the streaming phases
+  int mixed;   // 0: FP64, else the low-precision copy's sem_prec
+  int active;
+  int phase;  // SlotPhase, written by the device
+  int inner_total;
+  int inner_max;
+  int utiles;  // update tiles of its CG update (upd_num_tiles); partials of that update
+  double eta2;
+  int64_t E, L;
+  const double *D, *G, *b;
+  double *minv, *r, *p, *w, *x;
+  const float *Dlo;
+  const void *Glo;
+  float *minv32, *e, *rin, *pin, *win;
+  CgState *st, *st_in;
+  double *part_el, *part_rr, *part_rz;
+};
+
+// Compact per-slot status the host polls (written by the device).
+struct BatchStatus {
+  int phase;
+  int done;
+  int iters;        // FP64 iterations, or total inner iterations (mixed)
+  int outer_iters;  // mixed: outer steps
+  double rnorm2, bnorm2;
+};
+
+// Operator work of a batched iteration is binned by class and order: class 0
+// is the FP64 CG iterations of FP64 solves, classes 1 and 2 the FP32 and BF16
+// inner iterations of mixed solves, class 3 the FP64 true-residual operator
+// of their outer steps.  Lists kBatchFinList and kBatchFinList + 1 hold the
+// streaming tiles of the FP64 and mixed solves whose phase ends this
+// iteration (rebuilt after the beta launch), kBatchResidList those of the
+// mixed solves computing an outer true residual; after them come the update
+// tiles of the CG update, per order, of the FP64 solves (family 0, the slots
+// of bin (0, N)) and of the inner solves (family 1, bins (1, N) and (2, N)).
+constexpr int kBatchOrders = 11;  // batches take orders 1..11
+constexpr int kBatchClasses = 4;
+constexpr int kBatchBins = kBatchClasses * kBatchOrders;
+constexpr int kBatchFinList = kBatchBins;
+constexpr int kBatchResidList = kBatchBins + 2;
+constexpr int kBatchUpdLists = kBatchBins + 3;
+constexpr int kBatchLists = kBatchUpdLists + 2 * kBatchOrders;
+constexpr int kBatchMaxSlots = 4096;
+__host__ __device__ inline int batch_bin(int cls, int N) { return cls * kBatchOrders + (N - 1); }
+__host__ __device__ inline int batch_upd_list(int fam, int N) {
+  return kBatchUpdLists + fam * kBatchOrders + (N - 1);
+}
+
+// Work lists that the schedule kernel rebuilds on the device at the start of
+// every batched iteration (kBatchLists lists, max_slots entries each): the
+// slots with work in the bin in ascending order, the exclusive prefix sums of
+// their item counts (one more entry: the total), and [count, total].
+struct BatchSched {
+  int *meta;
+  int *slot;
+  int *prefix;
+  int max_slots;
+};
+
+// Elements per operator item, by class and order (index 1..11).
+struct BatchTiles {
+  int epb[kBatchClasses][kBatchOrders + 1];
+};
+
+}  // namespace semk

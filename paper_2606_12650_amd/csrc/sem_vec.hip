@@ -18,100 +18,17 @@
 #include "sem_cg_dev.h"
 #include "sem_device.h"
 #include "sem_internal.h"
+#include "sem_kernels.h"
+#include "sem_rtc.h"
 
 namespace semk {
 namespace {
-
-// ------------------------------------------------------------ gather-scatter
-template <int N1, int MODE, typename T>
-__global__ void __launch_bounds__(kVecThreads)
-    gather_kernel(Box b, int64_t L, int64_t ntiles, const T *__restrict__ wl, T *__restrict__ out) {
-  const int64_t tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
-  const int64_t base = tile * kVecTile + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kVecItems; ++u) {
-    const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < L) {
-      const Node<N1> n = node_at<N1>(b, idx);
-      double v;
-      if (MODE != kGatherAssembled && n.boundary) {
-        v = 0.0;
-      } else {
-        v = gather_copies<N1>(wl, b, n, idx);
-        if (MODE == kGatherInverse) v = 1.0 / v;
-      }
-      out[idx] = (T)v;
-    }
-  }
-}
-
-// The same gather on element-column tiles (copies paired across faces, as
-// in the CG update), used where that tile is the update's tile.
-template <int N1, int MODE, typename T>
-__global__ void __launch_bounds__((UpdTile<N1, T>::BLOCK))
-    gather_col_kernel(Box b, int64_t ntiles, const T *__restrict__ wl, T *__restrict__ out) {
-  using U = UpdTile<N1, T>;
-  __shared__ double sA[U::LDS];
-  const int64_t tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
-  const ColumnPos<N1, T> p(b, tile, (int)threadIdx.x);
-  double S[U::KN];
-  column_copy_sums<N1, T>(p, wl, sA, S);
-#pragma unroll
-  for (int kk = 0; kk < U::KN; ++kk) {
-    const int k = p.kb + kk;
-    if (p.live && k <= U::N) {
-      double v = S[kk];
-      if (MODE != kGatherAssembled && p.boundary(b, k))
-        v = 0.0;
-      else if (MODE == kGatherInverse)
-        v = 1.0 / v;
-      out[p.col0 + (int64_t)k * U::COLS] = (T)v;
-    }
-  }
-}
-
-// ------------------------------------------------------------ CG kernels
-template <int N1>
-__global__ void __launch_bounds__(kVecThreads)
-    cg_init_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ bvec,
-                   double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
-                   const double *__restrict__ minv, double *__restrict__ part_rz,
-                   double *__restrict__ part_bb) {
-  __shared__ double sred[kVecThreads / 64];
-  const int64_t tile = xcd_tile(ntiles);
-  TileSums t{0.0, 0.0};
-  if (tile < ntiles) t = cg_init_tile<N1>(b, L, tile, bvec, x, r, p, minv, sred);
-  if (threadIdx.x == 0) {
-    part_rz[tile] = t.a;
-    part_bb[tile] = t.b;
-  }
-}
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_init_finish_kernel(CgState *st, const double *__restrict__ part_rz,
                           const double *__restrict__ part_bb, int64_t n) {
   __shared__ double sred[kFinThreads / 64];
   cg_init_step(st, part_rz, part_bb, n, sred);
-}
-
-template <int N1, typename TV>
-__global__ void __launch_bounds__((UpdTile<N1, TV>::BLOCK))
-    cg_update_kernel(Box b, int64_t ntiles, TV *__restrict__ r, const TV *__restrict__ w,
-                     const TV *__restrict__ minv, CgState *__restrict__ st,
-                     double *__restrict__ part_rr, double *__restrict__ part_rz) {
-  __shared__ double sred[UpdTile<N1, TV>::BLOCK / 64];
-  __shared__ double sA[UpdTile<N1, TV>::LDS];
-  if (st->done) return;
-  const double alpha = st->alpha;
-  const int64_t tile = xcd_tile(ntiles);
-  TileSums t{0.0, 0.0};
-  if (tile < ntiles) t = cg_update_tile<N1, TV>(b, tile, r, w, minv, alpha, sA, sred, (int)threadIdx.x);
-  if (threadIdx.x == 0) {
-    part_rr[tile] = t.a;
-    part_rz[tile] = t.b;
-  }
 }
 
 __global__ void __launch_bounds__(kFinThreads)
@@ -197,18 +114,6 @@ __global__ void __launch_bounds__(kVecThreads)
   double rr = 0.0;
   if (tile < ntiles && done == kRunning) rr = residual_tile<N1>(b, L, tile, bvec, wl, r, sred);
   if (threadIdx.x == 0) part[tile] = rr;
-}
-
-// ------------------------------------------------------------ setup helpers
-template <int N1>
-__global__ void __launch_bounds__(kVecThreads)
-    fill_c_kernel(Box b, int64_t L, double *__restrict__ c) {
-  const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
-#pragma unroll
-  for (int u = 0; u < kVecItems; ++u) {
-    const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < L) c[idx] = node_at<N1>(b, idx).inv_mult();
-  }
 }
 
 // ------------------------------------------------------------ generic vectors
@@ -377,6 +282,7 @@ hipError_t gather_typed(const Box &b, const T *wl, T *out, int mode, hipStream_t
 }
 
 hipError_t launch_gather(const Box &b, const double *wl, double *out, int mode, hipStream_t s) {
+  if (rtc_order(b.N)) return b.L() == 0 ? hipSuccess : rtc_gather(b, wl, out, mode, s);
   return gather_typed<double>(b, wl, out, mode, s);
 }
 
@@ -389,9 +295,14 @@ hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r
                           hipStream_t s) {
   const int64_t L = b.L();
   const int64_t nt = vec_num_blocks(L);
-  DISPATCH_N(b, cg_init_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, bvec, x, r, p,
-             minv, part_a, part_b);
-  hipError_t e = hipGetLastError();
+  hipError_t e;
+  if (rtc_order(b.N)) {
+    e = rtc_cg_init(b, bvec, x, r, p, minv, part_a, part_b, s);
+  } else {
+    DISPATCH_N(b, cg_init_kernel, xcd_vec_grid(L), dim3(kVecThreads), 0, s, b, L, nt, bvec, x, r, p,
+               minv, part_a, part_b);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_init_finish_kernel, dim3(1), dim3(kFinThreads), 0, s, st, part_a, part_b,
                      vec_grid_blocks(L));
@@ -411,6 +322,7 @@ hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part
 
 hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
+  if (rtc_order(b.N)) return b.E() == 0 ? hipSuccess : rtc_cg_update(b, r, w, minv, st, part_rr, part_rz, s);
   return update_typed<double>(b, r, w, minv, st, part_rr, part_rz, s);
 }
 
@@ -464,6 +376,7 @@ hipError_t launch_outer_step(const Box &b, const double *bvec, const double *w64
 hipError_t launch_fill_c(const Box &b, double *c, hipStream_t s) {
   const int64_t L = b.L();
   if (L == 0) return hipSuccess;
+  if (rtc_order(b.N)) return rtc_fill_c(b, c, s);
   DISPATCH_N(b, fill_c_kernel, vec_grid(L), dim3(kVecThreads), 0, s, b, L, c);
   return hipGetLastError();
 }

@@ -73,6 +73,9 @@ class SemOperator:
         self.desc = mesh_desc(nelx, nely, nelz, order, deform_amp, lowprec, mfma)
         nbytes = int(lib.sem_workspace_bytes(ctypes.byref(self.desc)))
         if nbytes == 0:
+            # the set-up's own check names the reason (SEM_ERR_ARG or SEM_ERR_UNSUPPORTED)
+            rc = lib.sem_setup(ctypes.byref(self.desc), None, 0, None, ctypes.byref(ctypes.c_void_p()))
+            L.check("sem_setup", rc)
             raise ValueError(f"invalid mesh descriptor {nelx}x{nely}x{nelz} N={order}")
         self.ws_bytes = nbytes
         # 256 extra bytes so the workspace can be aligned to 256.
@@ -124,13 +127,16 @@ class SemOperator:
 
     def cg(self, b: torch.Tensor, x: torch.Tensor | None = None, rtol: float = 1e-8,
            max_iter: int = 0, fixed_iter: int = 0, check_every: int = 0, mixed: bool = False,
-           inner_rtol: float = 0.0, inner_max: int = 0, raise_on_fail: bool = True):
-        """``sem_cg``: Jacobi-PCG from x = 0.  Returns (x, CgResult)."""
+           inner_rtol: float = 0.0, inner_max: int = 0, raise_on_fail: bool = True,
+           precond: bool = True):
+        """``sem_cg``: Jacobi-PCG from x = 0 (``precond=False``: plain CG).
+        Returns (x, CgResult)."""
         _check_vec(b, self.L, "b", self.device)
         x = self.empty() if x is None else x
         _check_vec(x, self.L, "x", self.device)
         opts = L.SemCgOpts(float(rtol), int(max_iter), int(fixed_iter), int(bool(mixed)),
-                           int(check_every), float(inner_rtol), int(inner_max), 0)
+                           int(check_every), float(inner_rtol), int(inner_max),
+                           L.SEM_PRECOND_JACOBI if precond else L.SEM_PRECOND_NONE)
         info = L.SemCgInfo()
         rc = L.lib().sem_cg(self._ctx, _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(info),
                             _stream(self.device))
@@ -176,9 +182,11 @@ def gs_csr_build(gid) -> tuple[torch.Tensor, torch.Tensor]:
     return offsets, ids[:copies.value]
 
 
-def gs(offsets: torch.Tensor, ids: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
+def gs(offsets: torch.Tensor, ids: torch.Tensor, w: torch.Tensor, check: bool = True) -> torch.Tensor:
     """``sem_gs``: in place, every copy of a row of (offsets, ids) receives the
-    sum of the row's copies.  offsets and ids are int32 tensors on w's device."""
+    sum of the row's copies.  offsets and ids are int32 tensors on w's device.
+    ``check`` compares offsets[-1] with ids.numel() (a device read; callers
+    timing repeated calls on checked rows pass False)."""
     n = w.numel()
     _check_vec(w, n, "w", w.device)
     for t, name in ((offsets, "offsets"), (ids, "ids")):
@@ -187,7 +195,10 @@ def gs(offsets: torch.Tensor, ids: torch.Tensor, w: torch.Tensor) -> torch.Tenso
     n_rows = offsets.numel() - 1
     if n_rows < 0:
         raise ValueError("offsets must hold n_rows + 1 entries")
-    L.check("sem_gs", L.lib().sem_gs(n_rows, _ptr(offsets), _ptr(ids), n, _ptr(w),
+    n_copies = ids.numel()
+    if check and int(offsets[-1].item()) != n_copies:
+        raise ValueError(f"ids holds {n_copies} entries but offsets[-1] = {int(offsets[-1].item())}")
+    L.check("sem_gs", L.lib().sem_gs(n_rows, _ptr(offsets), _ptr(ids), n_copies, n, _ptr(w),
                                      _stream(w.device)))
     return w
 
@@ -210,3 +221,4 @@ def vec_dot(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = None,
     L.check("vec_dot", L.lib().vec_dot(n, _ptr(x), _ptr(y), _ptr(wt), _ptr(out), _ptr(ws),
                                        ws.numel() * ws.element_size(), _stream(x.device)))
     return out
+

@@ -9,6 +9,7 @@ Tolerances (written here, derived in the design notes):
   CG, tolerance mode    both true residuals <= rtol (1 + 1e-3); iterations within 2
 """
 
+import ctypes
 import math
 import os
 
@@ -270,6 +271,48 @@ def test_cg_all_orders_ragged(N):
             or max(res.rel_res, info["rel_res"]) <= 1e-13)
     # continuity: every copy of a node holds the same bits of x
     assert _same_on_copies(pr, x)
+
+
+@pytest.mark.parametrize("mesh,N", [((5, 3, 2), 3), ((3, 3, 2), 7), ((3, 2, 3), 9), ((2, 3, 2), 11)])
+@MFMA
+def test_plain_cg_matches_oracle(mesh, N, mfma):
+    """The unpreconditioned CG (SEM_PRECOND_NONE, the paper's Nekbone CG)
+    against the oracle's CG with Minv = mask: 20 fixed iterations, then
+    tolerance mode; the same context then runs Jacobi-PCG again and must give
+    the bits of a Jacobi-PCG run that never saw the plain mode (the captured
+    iteration graph is keyed by the preconditioner)."""
+    pr = op.Problem(*mesh, N, 0.05)
+    b = workload.continuous_rhs(80 + N, *mesh, N)
+    A = sem.SemOperator(*mesh, N, 0.05, device=DEV, mfma=mfma)
+    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.mask, pr.c, fixed_iter=20)
+    xg, res = A.cg(_gpu(b), fixed_iter=20, precond=False)
+    assert res.iters == 20 and res.status == 0
+    x = _cpu(xg)
+    assert _c_norm(x - xr.reshape(-1), pr.c) / _c_norm(xr, pr.c) <= 1e-9
+    assert abs(res.rel_res - info["rel_res"]) <= 1e-6 * info["rel_res"]
+    assert _same_on_copies(pr, x)
+    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.mask, pr.c, rtol=1e-8)
+    xg, res = A.cg(_gpu(b), rtol=1e-8, precond=False)
+    assert res.status == 0 and abs(res.iters - info["iters"]) <= 2
+    tr = opcg.true_rel_residual(pr.ax, pr.shape4(b), pr.shape4(_cpu(xg)), pr.c)
+    assert tr <= 1e-8 * (1 + 1e-3)
+    xj, resj = A.cg(_gpu(b), rtol=1e-8)
+    B = sem.SemOperator(*mesh, N, 0.05, device=DEV, mfma=mfma)
+    xj2, resj2 = B.cg(_gpu(b), rtol=1e-8)
+    assert torch.equal(xj, xj2) and resj.iters == resj2.iters
+
+
+def test_precond_option_is_checked():
+    A = sem.SemOperator(2, 2, 2, 3, 0.0, lowprec="f32", device=DEV)
+    b = _gpu(workload.continuous_rhs(1, 2, 2, 2, 3))
+    lib = L.lib()
+    x = torch.empty_like(b)
+    info = L.SemCgInfo()
+    for precond, mixed in ((2, 0), (-1, 0), (L.SEM_PRECOND_NONE, 1)):
+        opts = L.SemCgOpts(1e-8, 0, 0, mixed, 0, 0.0, 0, precond)
+        rc = lib.sem_cg(A._ctx, sem.sem._ptr(b), sem.sem._ptr(x), ctypes.byref(opts), ctypes.byref(info),
+                        sem.sem._stream(A.device))
+        assert rc == L.SEM_ERR_ARG
 
 
 def test_cg_breakdown_and_cap_are_reported():

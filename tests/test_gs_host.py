@@ -54,6 +54,7 @@ def test_csr_build_errors():
 
 def test_gs_rejects_bad_sizes_before_launch():
     lib = L.lib()
-    assert lib.sem_gs(-1, None, None, 0, None, None) == L.SEM_ERR_ARG
-    assert lib.sem_gs(3, None, None, 10, None, None) == L.SEM_ERR_ARG
-    assert lib.sem_gs(0, None, None, -1, None, None) == L.SEM_ERR_ARG
+    assert lib.sem_gs(-1, None, None, 0, 0, None, None) == L.SEM_ERR_ARG
+    assert lib.sem_gs(3, None, None, 0, 10, None, None) == L.SEM_ERR_ARG
+    assert lib.sem_gs(0, None, None, 0, -1, None, None) == L.SEM_ERR_ARG
+    assert lib.sem_gs(0, None, None, -1, 0, None, None) == L.SEM_ERR_ARG

@@ -37,7 +37,7 @@ def test_workspace_bytes_host_only():
     assert 80 * Lpts <= nb < 80 * Lpts + 4 * 2 ** 20
     bad = L.SemMeshDesc(0, 1, 1, 7, 0.0, 0, 0)
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
-    bad = L.SemMeshDesc(1, 1, 1, 13, 0.0, 0, 0)
+    bad = L.SemMeshDesc(1, 1, 1, 16, 0.0, 0, 0)  # above the run-time compiled orders 13..15
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
     # unknown flag bits are refused; the matrix-core flag costs no memory
     for flags in (3, 4, -1):

@@ -43,7 +43,7 @@ def _legendre_coeffs_mp(N):
     return P1
 
 
-@pytest.mark.parametrize("N", range(2, 13))
+@pytest.mark.parametrize("N", range(2, 16))
 def test_gll_nodes_vs_mpmath(N):
     """Interior nodes are the roots of P_N'; weights 2/(N(N+1)P_N^2), at 50 digits."""
     with mpmath.workdps(50):
@@ -60,19 +60,23 @@ def test_gll_nodes_vs_mpmath(N):
     x, w = gll_nodes_weights(N)
     ulp = np.spacing(1.0)
     assert np.max(np.abs(x - xr)) <= 2 * ulp
-    assert np.max(np.abs(w - wr) / wr) <= 8 * ulp
+    # w = 2 / (N (N+1) P_N^2) with P_N from an N-step recurrence: its rounding
+    # grows with N (about one ulp per step, twice for the square), so above the
+    # built orders the bound is 2N ulp
+    assert np.max(np.abs(w - wr) / wr) <= (8 if N <= 12 else 2 * N) * ulp
 
 
-@pytest.mark.parametrize("N", range(1, 13))
+@pytest.mark.parametrize("N", range(1, 16))
 def test_gll_quadrature_exactness(N):
     x, w = gll_nodes_weights(N)
     assert abs(w.sum() - 2.0) < 1e-14
     for k in range(2 * N):
         exact = 0.0 if k % 2 else 2.0 / (k + 1)
         assert abs(np.sum(w * x ** k) - exact) < 2e-14, k
-    # Lobatto quadrature is not exact at degree 2N (a defining property).
+    # Lobatto quadrature is not exact at degree 2N (a defining property); the
+    # defect shrinks fast with N (3e-9 at N = 15), still far above rounding
     k = 2 * N
-    assert abs(np.sum(w * x ** k) - 2.0 / (k + 1)) > 1e-8
+    assert abs(np.sum(w * x ** k) - 2.0 / (k + 1)) > (1e-8 if N <= 12 else 1e-12)
 
 
 def test_deriv_closed_forms():
@@ -81,7 +85,7 @@ def test_deriv_closed_forms():
                                atol=1e-15)
 
 
-@pytest.mark.parametrize("N", range(1, 13))
+@pytest.mark.parametrize("N", range(1, 16))
 def test_deriv_exact_on_polynomials(N):
     x, _ = gll_nodes_weights(N)
     D = deriv_matrix(N)
@@ -92,7 +96,7 @@ def test_deriv_exact_on_polynomials(N):
         assert np.max(np.abs(d - exact)) <= 1e-12 * scale * max(1, k), (N, k)
 
 
-@pytest.mark.parametrize("N", range(1, 13))
+@pytest.mark.parametrize("N", range(1, 16))
 def test_deriv_three_routes_agree(N):
     """Barycentric (oracle) vs the Legendre closed form
     D_ij = P_N(x_i)/(P_N(x_j)(x_i-x_j)), D_00 = -N(N+1)/4, D_NN = N(N+1)/4,
