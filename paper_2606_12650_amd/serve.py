@@ -67,22 +67,33 @@ class ServeStats:
     wall: float = 0.0
     max_active: int = 0
     peak_bytes: int = 0
+    gpu_busy_s: float = 0.0  # time the batch stream spent in batched steps (GPU executor)
 
-    def summary(self) -> dict:
-        lat = np.array([c.latency for c in self.completions]) if self.completions else np.zeros(1)
-        ok = sum(1 for c in self.completions if c.status == 0)
+    def summary(self, warmup: int = 0) -> dict:
+        """Latency percentiles and throughput over the requests after the
+        first ``warmup`` (in arrival order).  Throughput counts the timed
+        requests that converged, over the window from the first timed
+        arrival to the last timed completion."""
+        done = sorted(self.completions, key=lambda c: c.arrival)
+        timed = done[warmup:] if warmup < len(done) else []
+        lat = np.array([c.latency for c in timed]) if timed else np.zeros(1)
+        ok = sum(1 for c in timed if c.status == 0)
+        window = (max(c.finished for c in timed) - min(c.arrival for c in timed)) if timed else 0.0
         return {
             "requests": len(self.completions) + len(self.rejected),
             "completed": len(self.completions),
-            "converged": ok,
+            "converged": sum(1 for c in self.completions if c.status == 0),
             "rejected": len(self.rejected),
-            "solves_per_s": ok / self.wall if self.wall > 0 else 0.0,
+            "warmup": min(warmup, len(done)),
+            "timed": len(timed),
+            "solves_per_s": ok / window if window > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(lat.mean()),
             "wall_s": self.wall,
             "max_active": self.max_active,
             "peak_bytes": self.peak_bytes,
+            "gpu_busy_frac": self.gpu_busy_s / self.wall if self.wall > 0 else 0.0,
         }
 
 
@@ -99,6 +110,14 @@ class Scheduler:
     ``step()``, ``poll() -> [(slot, result)]``, ``release(slot)`` and
     ``active``; ``clock()`` returns seconds since the start and
     ``sleep(dt)`` waits (both injectable for tests).
+
+    An executor that also provides ``prepare(req) -> token``,
+    ``admit_prepared(token) -> slot`` and ``launch_step()`` (asynchronous,
+    finished by ``poll``) gets admission off the device's critical path: the
+    expensive part of admitting (set-up of the operator and the right-hand
+    side) runs while the batched step of the admitted requests is on the
+    GPU, and only the cheap insertion of prepared requests into the batch
+    happens between steps.  A prepared request holds its slot and memory.
     """
 
     def __init__(self, executor, hbm_budget: int, max_slots: int, clock=None, sleep=None):
@@ -110,6 +129,8 @@ class Scheduler:
         self.sleep = sleep or time.sleep
 
     def run(self, requests: list[Request]) -> ServeStats:
+        if all(hasattr(self.ex, a) for a in ("prepare", "admit_prepared", "launch_step")):
+            return self._run_overlapped(requests)
         stats = ServeStats()
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue: deque = deque()
@@ -150,13 +171,77 @@ class Scheduler:
                 if wait > 0:
                     self.sleep(wait)
         stats.wall = self.clock() - start
+        stats.gpu_busy_s = getattr(self.ex, "busy_s", 0.0)
+        return stats
+
+    def _run_overlapped(self, requests: list[Request]) -> ServeStats:
+        stats = ServeStats()
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        queue: deque = deque()
+        prepared: deque = deque()  # (request, token, footprint, admitted time)
+        active: dict = {}  # slot -> (request, footprint, admitted time)
+        used = 0
+        start = self.clock()
+
+        def take_arrivals():
+            now = self.clock() - start
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+
+        def prepare_queued():
+            nonlocal used
+            while queue and len(active) + len(prepared) < self.max_slots:
+                req = queue[0]
+                fp = self.ex.footprint(req)
+                if fp > self.budget:  # can never fit: refuse rather than block the queue
+                    queue.popleft()
+                    stats.rejected.append(req.index)
+                    continue
+                if used + fp > self.budget:
+                    break
+                queue.popleft()
+                adm = self.clock() - start
+                prepared.append((req, self.ex.prepare(req), fp, adm))
+                used += fp
+                stats.peak_bytes = max(stats.peak_bytes, used)
+
+        while pending or queue or prepared or active:
+            take_arrivals()
+            if not active and not prepared:
+                prepare_queued()  # nothing on the device: prepare now
+            while prepared:
+                req, token, fp, adm = prepared.popleft()
+                active[self.ex.admit_prepared(token)] = (req, fp, adm)
+            stats.max_active = max(stats.max_active, len(active))
+            if active:
+                self.ex.launch_step()
+                # the step runs on the device: admit what has arrived meanwhile
+                take_arrivals()
+                prepare_queued()
+                done = self.ex.poll()
+                tnow = self.clock() - start
+                for slot, res in done:
+                    req, fp, adm = active.pop(slot)
+                    self.ex.release(slot)
+                    used -= fp
+                    stats.completions.append(Completion(req.index, req.arrival, adm, tnow, res.iters,
+                                                        res.outer_iters, res.status, res.rel_res))
+            elif pending and not queue and not prepared:
+                wait = pending[0].arrival - (self.clock() - start)
+                if wait > 0:
+                    self.sleep(wait)
+        stats.wall = self.clock() - start
+        stats.gpu_busy_s = getattr(self.ex, "busy_s", 0.0)
         return stats
 
 
 class GpuExecutor:
-    """Device side of the scheduler: one SemBatch; each admitted request gets
-    its own SemOperator (set up on the GPU) and a right-hand side drawn on
-    the GPU from its seed."""
+    """Device side of the scheduler: one SemBatch on the batch stream; each
+    admitted request gets its own SemOperator and a right-hand side drawn on
+    the GPU from its seed, both made on a side stream while the batched step
+    runs (``prepare``), then joined to the batch between steps
+    (``admit_prepared``).  HIP events around every step measure the time the
+    batch stream is busy."""
 
     def __init__(self, device="cuda", max_slots=64, mixed: str | None = "f32", iters_per_step=10,
                  tiles: dict | None = None,
@@ -170,6 +255,8 @@ class GpuExecutor:
         self.mixed = mixed
         self.iters = int(iters_per_step)
         self.rtol = rtol
+        self.stream = torch.cuda.current_stream(self.device)  # the batch stream
+        self.setup_stream = torch.cuda.Stream(device=self.device)
         self.batch = SemBatch(max_slots, device=self.device)
         for prec, per_order in (tiles or {}).items():  # {"f64" / "f32" / "bf16": {order: epb}}
             for order, epb in per_order.items():
@@ -177,28 +264,57 @@ class GpuExecutor:
         self.slots: dict = {}
         self.keep = keep_solutions
         self.solutions: dict = {}  # request index -> x (when keep_solutions)
+        self.busy_s = 0.0
+        self._events = None
 
     def footprint(self, req: Request) -> int:
         from .sem import workspace_bytes
 
         return workspace_bytes(req.nx, req.ny, req.nz, req.N, req.amp, self.mixed) + 16 * req.L + 512
 
-    def admit(self, req: Request) -> int:
+    def prepare(self, req: Request):
+        """Set up the request's operator and right-hand side on the side
+        stream (sem_setup waits for that stream only)."""
         import workload
 
         from .sem import SemOperator
 
-        op = SemOperator(req.nx, req.ny, req.nz, req.N, req.amp, lowprec=self.mixed, device=self.device)
-        b = workload.continuous_rhs_device(req.rhs_seed, req.nx, req.ny, req.nz, req.N, self.device)
+        torch = self.torch
+        with torch.cuda.stream(self.setup_stream):
+            op = SemOperator(req.nx, req.ny, req.nz, req.N, req.amp, lowprec=self.mixed, device=self.device)
+            b = workload.continuous_rhs_device(req.rhs_seed, req.nx, req.ny, req.nz, req.N, self.device)
+        self.setup_stream.synchronize()
+        # the batch stream uses these from now on
+        op._ws_raw.record_stream(self.stream)
+        b.record_stream(self.stream)
+        return req, op, b
+
+    def admit_prepared(self, token) -> int:
+        req, op, b = token
         slot = self.batch.add(op, b, rtol=self.rtol, mixed=self.mixed is not None)
         self.slots[slot] = req
         return slot
 
-    def step(self) -> None:
+    def admit(self, req: Request) -> int:
+        return self.admit_prepared(self.prepare(req))
+
+    def launch_step(self) -> None:
+        torch = self.torch
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
         self.batch.step(self.iters)
+        e1.record(self.stream)
+        self._events = (e0, e1)
+
+    def step(self) -> None:
+        self.launch_step()
 
     def poll(self):
-        fin, _ = self.batch.poll()
+        fin, _ = self.batch.poll()  # waits for the step
+        if self._events is not None:
+            self.busy_s += self._events[0].elapsed_time(self._events[1]) / 1e3
+            self._events = None
         return fin
 
     def release(self, slot: int):

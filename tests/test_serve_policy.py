@@ -124,3 +124,88 @@ def test_latency_statistics():
     assert s["completed"] == 100 and s["converged"] == 100
     assert abs(s["p50_latency_s"] - float(np.percentile(lat, 50))) < 1e-12
     assert s["p99_latency_s"] >= s["p50_latency_s"] > 0
+
+
+class OverlapStub(StubExecutor):
+    """The same work model, with admission split as the GPU executor splits
+    it: ``prepare`` costs host time (the set-up), ``launch_step`` starts a
+    1 ms device step and returns at once, ``poll`` waits for its end."""
+
+    SETUP = 0.4e-3
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.step_end = None
+        self.busy_s = 0.0
+
+    def prepare(self, req):
+        self.clock.t += self.SETUP
+        return req
+
+    def admit_prepared(self, req):
+        return super().admit(req)
+
+    def admit(self, req):  # the sequential path: set-up then insertion
+        return self.admit_prepared(self.prepare(req))
+
+    def launch_step(self):
+        self.step_end = self.clock.t + 1e-3
+        self.busy_s += 1e-3
+        for s in list(self.left):
+            r, n = self.left[s]
+            self.left[s] = (r, n - 1)
+
+    def poll(self):
+        self.clock.t = max(self.clock.t, self.step_end)
+        return super().poll()
+
+
+class SequentialStub(OverlapStub):
+    """Same costs, without the overlap (the executor interface of the
+    sequential path only)."""
+
+
+    def __getattribute__(self, name):
+        if name in ("prepare", "admit_prepared", "launch_step"):
+            raise AttributeError(name)
+        return object.__getattribute__(self, name)
+
+    def admit(self, req):
+        self.clock.t += self.SETUP
+        return StubExecutor.admit(self, req)
+
+    def step(self):
+        OverlapStub.launch_step(self)
+        self.clock.t = max(self.clock.t, self.step_end)
+
+
+def test_overlapped_admission_keeps_policy_and_hides_setup():
+    reqs = _requests(n=80, rate=3000.0)
+    results = {}
+    for name, cls in (("overlap", OverlapStub), ("sequential", SequentialStub)):
+        clk = Clock()
+        ex = cls(clk)
+        budget = int(2e6 * 100)
+        stats = Scheduler(ex, budget, 8, clock=clk, sleep=clk.sleep).run(reqs)
+        s = stats.summary()
+        assert s["completed"] + s["rejected"] == len(reqs)
+        assert all(u <= budget for _, _, _, u in ex.log)
+        assert stats.max_active <= 8
+        admitted = [i for _, ev, i, _ in ex.log if ev == "admit"]
+        fits = [r.index for r in sorted(reqs, key=lambda r: r.arrival) if r.L * 100 <= budget]
+        assert admitted == fits  # first come, first served
+        results[name] = s
+    # the set-ups overlap the device steps: less wall time, a busier device
+    assert results["overlap"]["wall_s"] < results["sequential"]["wall_s"]
+    assert results["overlap"]["gpu_busy_frac"] > results["sequential"]["gpu_busy_frac"]
+
+
+def test_summary_excludes_warmup():
+    clk = Clock()
+    ex = StubExecutor(clk)
+    reqs = _requests(n=50)
+    stats = Scheduler(ex, 10 ** 12, 16, clock=clk, sleep=clk.sleep).run(reqs)
+    s0, s10 = stats.summary(), stats.summary(warmup=10)
+    assert s0["timed"] == 50 and s10["timed"] == 40 and s10["warmup"] == 10
+    timed = sorted(stats.completions, key=lambda c: c.arrival)[10:]
+    assert abs(s10["p50_latency_s"] - float(np.percentile([c.latency for c in timed], 50))) < 1e-12
