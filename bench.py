@@ -40,6 +40,16 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def _cg_source_hash() -> str:
+    """Hash of every source the CG iteration's kernels are built from."""
+    h = hashlib.sha256()
+    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h",
+              "sem_cg_dev.h", "sem_vec.hip"):
+        with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def _traffic_from_profile(kernel_hash: str):
     """HBM bytes per launch of the A.u kernel from committed rocprofv3 counter
     runs, if they were taken on the current kernel source; else None."""
@@ -53,37 +63,128 @@ def _traffic_from_profile(kernel_hash: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(seconds_target: float = 15.0):
-    """The FP64 NumPy oracle's Jacobi-PCG on a bounded sample of the workload:
-    a 12x12x12 block of the same deformed N = 7 mesh family, timed per
-    iteration and scaled to GDOF/s (setup excluded, as on the GPU)."""
+def _cg_traffic_frac(iters: int, wall: float):
+    """HBM bytes the CG iterations actually moved (operator and update
+    kernels, from the committed counter runs, while the kernel source is
+    unchanged) over the solve time, as a fraction of the peak; None without
+    matching counters."""
+    path = os.path.join(ROOT, "profiles", "ax_f64_n7_e32768_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("cg_source_hash") != _cg_source_hash():
+        return None
+    per_iter = 0.0
+    for name, v in d.get("all_kernels", {}).items():
+        if name.startswith("void semk::(anonymous namespace)::ax_mfma_kernel<8, semk::PrecF64, true>") or \
+                name.startswith("void semk::(anonymous namespace)::cg_update_kernel<8, double>"):
+            per_iter += v["hbm_bytes"]
+    if per_iter == 0.0:
+        return None
+    return per_iter * iters / wall / 1e9 / HBM_PEAK_GBS
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_timed(fn, reps: int):
+    """Best of `reps` wall times of fn() and the cores it used (CPU time over
+    wall time of the best run)."""
+    best, cores = float("inf"), 1.0
+    for _ in range(reps):
+        t0, c0 = time.perf_counter(), time.process_time()
+        fn()
+        wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+        if wall < best:
+            best, cores = wall, cpu / max(wall, 1e-9)
+    return best, cores
+
+
+def cpu_baseline(gpu_iters_c2: int, include_c2: bool = True):
+    """The FP64 NumPy oracle, as it stands, timed on this host's cores.
+
+    C1 (4x4x4 affine box, N = 7): one masked A.u, 50 Jacobi-PCG iterations,
+    axpy and dot on 32768 entries.  C2 (the benchmarked 32x32x32 deformed box
+    at N = 7): one masked A.u and three PCG iterations, the per-iteration time
+    multiplied by the iteration count of the GPU solve to 1e-8 (setup
+    excluded, as on the GPU).  Each at two settings: every host core allowed
+    to the BLAS / OpenMP pools (OMP_NUM_THREADS = nproc), and one core.  The
+    cores a setting actually used are measured (CPU time over wall time): the
+    oracle's sum factorisation is NumPy einsum, which runs on one core either
+    way.  Best of 3 wall times."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import workload
     from oracle import operator as op
     from oracle import pcg as opcg
 
-    nx = ny = nz = 12
-    N, amp = 7, 0.05
-    pr = op.Problem(nx, ny, nz, N, amp)
-    b = pr.shape4(workload.continuous_rhs(4, nx, ny, nz, N))
-    # one short run to size the sample to about `seconds_target`
-    t0 = time.perf_counter()
-    opcg.pcg(pr.ax, b, pr.minv, pr.c, fixed_iter=2)
-    per_it = (time.perf_counter() - t0) / 2
-    iters = max(3, min(200, int(seconds_target / max(per_it, 1e-6))))
-    t0 = time.perf_counter()
-    opcg.pcg(pr.ax, b, pr.minv, pr.c, fixed_iter=iters)
-    dt = time.perf_counter() - t0
-    gdofs = pr.E * N ** 3 * iters / dt / 1e9
+    nproc = os.cpu_count() or 1
+    settings = {}
+    N = 7
+    c1 = op.Problem(4, 4, 4, N, 0.0)
+    u1 = c1.shape4(workload.continuous_rhs(1, 4, 4, 4, N))
+    b1 = c1.shape4(workload.continuous_rhs(2, 4, 4, 4, N))
+    rng = np.random.default_rng(3)
+    xa, ya = rng.uniform(-1.0, 1.0, c1.L), rng.uniform(-1.0, 1.0, c1.L)
+    c2 = None
+    if include_c2:
+        t0 = time.perf_counter()
+        c2 = op.Problem(32, 32, 32, N, 0.05)
+        b2 = c2.shape4(workload.continuous_rhs(4, 32, 32, 32, N))
+        c2_setup = time.perf_counter() - t0
+    for label, lim in (("all_cores", nproc), ("one_core", 1)):
+        with threadpool_limits(lim):
+            row = {"threads_allowed": lim}
+            t, cores = _cpu_timed(lambda: c1.ax(u1), 3)
+            row["c1_ax_us"], row["c1_ax_cores"] = t * 1e6, cores
+            t, cores = _cpu_timed(lambda: opcg.pcg(c1.ax, b1, c1.minv, c1.c, fixed_iter=50), 3)
+            row["c1_pcg50_ms"], row["c1_pcg_cores"] = t * 1e3, cores
+            row["c1_pcg_us_per_iter"] = t / 50 * 1e6
+            t, _ = _cpu_timed(lambda: ya + 0.5 * xa, 3)
+            row["c1_axpy_us"] = t * 1e6
+            t, _ = _cpu_timed(lambda: float(np.dot(xa, ya)), 3)
+            row["c1_dot_us"] = t * 1e6
+            if c2 is not None:
+                t, cores = _cpu_timed(lambda: c2.ax(b2), 2)
+                row["c2_ax_s"], row["c2_ax_cores"] = t, cores
+                row["c2_ax_gdofs"] = c2.E * N ** 3 / t / 1e9
+                t, cores = _cpu_timed(lambda: opcg.pcg(c2.ax, b2, c2.minv, c2.c, fixed_iter=3), 1)
+                per_it = t / 3
+                row["c2_pcg_s_per_iter"], row["c2_pcg_cores"] = per_it, cores
+                row["c2_pcg_gdofs"] = c2.E * N ** 3 / per_it / 1e9
+                row["c2_solve_s_extrapolated"] = per_it * gpu_iters_c2
+                row["c2_solves_per_s_extrapolated"] = 1.0 / (per_it * gpu_iters_c2)
+            settings[label] = row
+    main_row = settings["all_cores"]
+    if c2 is not None:
+        value = main_row["c2_pcg_gdofs"]
+        cores_used = main_row["c2_pcg_cores"]
+        sample = (f"FP64 NumPy oracle Jacobi-PCG on the benchmarked 32x32x32 deformed N=7 mesh, "
+                  f"3 iterations timed (setup {c2_setup:.0f} s excluded), GDOF/s per Eq. gdofs; "
+                  f"solve time = per-iteration time x {gpu_iters_c2} GPU iterations; C1 rows in 'settings'")
+    else:
+        value = main_row["c1_pcg50_ms"] and c1.E * N ** 3 * 50 / (main_row["c1_pcg50_ms"] / 1e3) / 1e9
+        cores_used = main_row["c1_pcg_cores"]
+        sample = "FP64 NumPy oracle, C1 only (4x4x4 affine N=7, 50 PCG iterations)"
     return {
-        "value": gdofs,
+        "value": value,
         "unit": "GDOF/s",
-        "cores": 1,
+        "cores": round(cores_used, 2),
         "kind": "oracle",
-        "sample": f"oracle FP64 Jacobi-PCG, {iters} iterations on the 12x12x12 deformed N=7 mesh "
-                  f"(E=1728, same element shape as the timed 32^3 mesh), {dt:.1f} s; single-threaded "
-                  f"NumPy (host nproc={os.cpu_count()})",
+        "sample": sample,
+        "nproc": nproc,
+        "cpu_model": _cpu_model(),
+        "settings": settings,
     }
 
 
@@ -95,6 +196,189 @@ def _timed(fn):
     r = fn()
     torch.cuda.synchronize()
     return time.perf_counter() - t0, r
+
+
+def _graph_time(fn, reps: int, stream, runs: int = 5):
+    """Per-call time of fn() (a launch sequence on `stream`): `reps` calls
+    captured once as a HIP graph, one untimed replay, then `runs` replays
+    timed with HIP events on that stream.  Returns (mean, min) seconds per
+    call over the runs."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(runs):
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        g.replay()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        per.append(a0.elapsed_time(a1) / 1e3 / reps)
+    del g
+    return sum(per) / len(per), min(per)
+
+
+# Stored bytes per element-local node of one A.u (read u and the six G
+# factors, write w): FP64 8 words; FP32 4-byte words; BF16 mode u and w FP32,
+# G as bfloat16.
+AX_BYTES_PER_POINT = {"f64": 64.0, "f32": 32.0, "bf16": 20.0}
+
+
+def _ax_kernel_name(prec: str, N: int, mfma: bool) -> str:
+    P = {"f64": "PrecF64", "f32": "PrecF32", "bf16": "PrecBF16"}[prec]
+    return f"{'ax_mfma_kernel' if mfma else 'ax_kernel'}<{N + 1}, {P}, false>"
+
+
+def _default_is_mfma(prec: str, N: int) -> bool:
+    # the library's per-order default (sem_internal.h op_uses_mfma)
+    return N >= 7 if prec in ("f64", "f32") else N >= 9
+
+
+def bench_ax_study(args, dev, orders=(7, 11)) -> dict:
+    """A.u alone (one element-local launch, SEM_AX_LOCAL) on the 32x32x32
+    deformed mesh at each order in FP64, FP32 and BF16 mode, with the default
+    element kernel of that order and precision and with the other one forced:
+    microseconds per launch (graph-replayed, the paper's 5-run protocol),
+    GDOF/s (E N^3 per launch) and the fraction of the 8 TB/s HBM peak on the
+    stored bytes per node."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    nx = ny = nz = 32
+    amp = 0.05
+    out = {}
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        for N in orders:
+            u64 = torch.from_numpy(workload.continuous_rhs(5, nx, ny, nz, N)).to(dev)
+            u32 = u64.to(torch.float32)
+            row = {}
+            for prec in ("f64", "f32", "bf16"):
+                dflt = _default_is_mfma(prec, N)
+                for mf in (dflt, not dflt):
+                    A = sem.SemOperator(nx, ny, nz, N, amp, lowprec=None if prec == "f64" else prec,
+                                        device=dev, mfma=mf)
+                    if prec == "f64":
+                        w = torch.empty_like(u64)
+                        fn = lambda: A.ax(u64, sem.LOCAL, out=w)  # noqa: E731
+                    else:
+                        w = torch.empty_like(u32)
+                        fn = lambda: A.ax_lowp(u32, sem.LOCAL, out=w)  # noqa: E731
+                    mean, best = _graph_time(fn, args.ax_reps, stream)
+                    bpp = AX_BYTES_PER_POINT[prec]
+                    gbs = bpp * A.L / mean / 1e9
+                    key = prec if mf == dflt else prec + "_alt"
+                    row[key] = {"kernel": _ax_kernel_name(prec, N, mf), "default": mf == dflt,
+                                "us": mean * 1e6, "best_run_us": best * 1e6,
+                                "gdofs": A.E * N ** 3 / mean / 1e9, "bytes_per_point": bpp,
+                                "gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+                    print(f"[bench] ax N={N} {key}: {row[key]}", file=sys.stderr, flush=True)
+                    A.close()
+                    del A, w
+            row["E"] = nx * ny * nz
+            row["L"] = nx * ny * nz * (N + 1) ** 3
+            out[f"N{N}"] = row
+            del u64, u32
+    torch.cuda.synchronize()
+    return out
+
+
+def profile_kernels(args, dev) -> dict:
+    """A short run of every kernel the counter summaries cover, for rocprofv3:
+    a plain 1 GiB device copy (the calibration of the HBM counters), the A.u
+    study (N = 7 and 11, FP64 / FP32 / BF16, both element tiles), and on the
+    32x32x32 deformed mesh at N = 7 and 11: 50 FP64 PCG iterations and 50
+    inner iterations of each mixed solver (one outer step)."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    out = {"ax_study": bench_ax_study(args, dev)}
+    stream = torch.cuda.Stream(device=dev)
+    with torch.cuda.stream(stream):
+        for N in (7, 11):
+            b = torch.from_numpy(workload.continuous_rhs(4, 32, 32, 32, N)).to(dev)
+            A = sem.SemOperator(32, 32, 32, N, 0.05, device=dev)
+            _, r = A.cg(b, fixed_iter=50, check_every=25)
+            out[f"cg_n{N}_fp64_50"] = r.iters
+            A.close()
+            for prec in ("f32", "bf16"):
+                A = sem.SemOperator(32, 32, 32, N, 0.05, lowprec=prec, device=dev)
+                _, r = A.cg(b, rtol=1e-8, mixed=True, max_iter=1, inner_max=50, check_every=25,
+                            raise_on_fail=False)
+                out[f"cg_n{N}_{prec}_inner"] = r.iters
+                A.close()
+            del b
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_c1(args, dev) -> dict:
+    """The small case (4x4x4 affine box, N = 7, E = 64, L = 32768; its 2 MB
+    stay in the caches, so it is timed per operation, not against HBM): one
+    masked A.u, one Jacobi-PCG iteration (50 fixed iterations), axpy and dot
+    on 32768 entries, and the time of an empty-work launch sequence."""
+    import torch
+
+    import workload
+    import paper_2606_12650_amd as sem
+
+    nx = ny = nz = 4
+    N = 7
+    stream = torch.cuda.Stream(device=dev)
+    out = {"E": 64, "N": N, "L": 32768}
+    with torch.cuda.stream(stream):
+        A = sem.SemOperator(nx, ny, nz, N, 0.0, device=dev)
+        u = torch.from_numpy(workload.continuous_rhs(1, nx, ny, nz, N)).to(dev)
+        b = torch.from_numpy(workload.continuous_rhs(2, nx, ny, nz, N)).to(dev)
+        w = torch.empty_like(u)
+        mean, _ = _graph_time(lambda: A.ax(u, sem.MASKED, out=w), 200, stream)
+        out["ax_masked_us"] = mean * 1e6
+        mean, _ = _graph_time(lambda: A.ax(u, sem.LOCAL, out=w), 200, stream)
+        out["ax_local_us"] = mean * 1e6
+        x = torch.empty_like(b)
+        A.cg(b, x, fixed_iter=50, check_every=50)
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            A.cg(b, x, fixed_iter=50, check_every=50)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out["pcg50_ms"] = sum(times) / len(times) * 1e3
+        out["pcg_us_per_iter"] = out["pcg50_ms"] / 50 * 1e3
+        rng = __import__("numpy").random.default_rng(3)
+        xa = torch.from_numpy(rng.uniform(-1.0, 1.0, 32768)).to(dev)
+        ya = torch.from_numpy(rng.uniform(-1.0, 1.0, 32768)).to(dev)
+        mean, _ = _graph_time(lambda: sem.vec_axpy(0.5, xa, ya), 200, stream)
+        out["axpy_us"] = mean * 1e6
+        ws = sem.vec_dot_workspace(32768, dev)
+        d = torch.empty(1, dtype=torch.float64, device=dev)
+        mean, _ = _graph_time(lambda: sem.vec_dot(xa, ya, out=d, ws=ws), 200, stream)
+        out["dot_us"] = mean * 1e6
+        # launch floor: an axpy over one entry (one work-group)
+        mean, _ = _graph_time(lambda: sem.vec_axpy(0.5, xa[:1], ya[:1]), 200, stream)
+        out["one_workgroup_launch_us"] = mean * 1e6
+        A.close()
+    torch.cuda.synchronize()
+    print(f"[bench] C1: {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def bench_precision_order(args, dev, N: int) -> dict:
@@ -308,6 +592,13 @@ def main(argv=None) -> int:
     ap.add_argument("--skip-serve", action="store_true", help="skip the serving study")
     ap.add_argument("--skip-n11", action="store_true", help="skip the precision study at N = 11")
     ap.add_argument("--skip-mixed", action="store_true", help="skip the mixed-precision solves at N = 7")
+    ap.add_argument("--skip-ax-study", action="store_true",
+                    help="skip the A.u study at N = 7 and 11 in FP64 / FP32 / BF16")
+    ap.add_argument("--skip-c1", action="store_true", help="skip the small-case (4x4x4, N = 7) timings")
+    ap.add_argument("--ax-only", action="store_true",
+                    help="only the A.u study; prints its JSON")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="a short run of every kernel the profiles cover (for rocprofv3); prints its JSON")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-rates", type=str, default="50,1000")
@@ -317,6 +608,16 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     if args.sweep and args.gpus == 1:
         return sweep(args)
+    if (args.ax_only or args.profile_kernels) and args.gpus == 1:
+        import torch
+
+        dev = torch.device("cuda", 0)
+        torch.cuda.set_device(dev)
+        if args.profile_kernels:
+            print(json.dumps(profile_kernels(args, dev)), flush=True)
+        else:
+            print(json.dumps({"ax_study": bench_ax_study(args, dev)}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the path is single-GPU; see the sharding notes in the design document)",
@@ -447,7 +748,7 @@ def main(argv=None) -> int:
         sem.gs(g_off, g_ids, wg)
         c0.record(stream)
         for _ in range(args.ax_reps):
-            sem.gs(g_off, g_ids, wg)
+            sem.gs(g_off, g_ids, wg, check=False)
         c1.record(stream)
         torch.cuda.synchronize()
         gs_s = c0.elapsed_time(c1) / 1e3 / args.ax_reps
@@ -510,6 +811,8 @@ def main(argv=None) -> int:
             del Am, xm
         torch.cuda.synchronize()
 
+    ax_study = None if args.skip_ax_study else bench_ax_study(args, dev)
+    c1 = None if args.skip_c1 else bench_c1(args, dev)
     precision_n11 = None if args.skip_n11 else bench_precision_order(args, dev, 11)
     batching = None if args.skip_batch else bench_batching(args, dev)
     serving = None if args.skip_serve else bench_serving(args, dev)
@@ -545,7 +848,11 @@ def main(argv=None) -> int:
         "mixed": {k: dict(v, speedup_vs_fp64=v["solves_per_s"] / (args.steps / wall)) for k, v in mixed.items()},
         "cg_iters_per_solve": timed_iters / args.steps,
         "cg_event_ms_per_step": ev_ms / args.steps,
-        "cg_hbm_floor_frac": cg_bytes_per_iter * timed_iters / wall / 1e9 / HBM_PEAK_GBS,
+        # the unfused (19 + 2s)-word floor per point and iteration over the
+        # time, against the peak: a throughput on a fixed byte count, not the
+        # bytes this design moves (17 words; see cg_hbm_traffic_frac)
+        "cg_unfused_floor_bytes_frac": cg_bytes_per_iter * timed_iters / wall / 1e9 / HBM_PEAK_GBS,
+        "cg_hbm_traffic_frac": _cg_traffic_frac(timed_iters, wall),
         "ax_local_us": ax_s * 1e6,
         "ax_masked_us": axm_s * 1e6,
         "ax_gdofs": gdof / ax_s / 1e9,
@@ -571,6 +878,10 @@ def main(argv=None) -> int:
             "kernel_source_hash": khash,
         },
     }
+    if ax_study is not None:
+        out["ax_study"] = ax_study
+    if c1 is not None:
+        out["c1"] = c1
     if precision_n11 is not None:
         out["precision_n11"] = precision_n11
     if batching is not None:
@@ -579,7 +890,7 @@ def main(argv=None) -> int:
         out["serving"] = serving
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(int(round(timed_iters / args.steps)))
     print(json.dumps(out), flush=True)
     return 0
 
