@@ -17,6 +17,8 @@
  *  - Pointers named *_dev are device pointers (HBM).  The library allocates
  *    no device memory: every device buffer, including the workspace, belongs
  *    to the caller and must stay alive while work that uses it is pending.
+ *    (The one library-owned buffer is the fixed partials array of
+ *    vec_dot_noalloc, part of the library's code object.)
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are asynchronous on that stream unless stated otherwise.
  *  - "L-vector": element-local storage of a nodal field, E*(N+1)^3 doubles,
@@ -204,6 +206,23 @@ size_t vec_dot_workspace_bytes(int64_t n);
  * device double; dev_ws holds vec_dot_workspace_bytes(n) bytes. */
 int vec_dot(int64_t n, const double *x_dev, const double *y_dev, const double *wt_dev,
             double *out_dev, void *dev_ws, size_t ws_bytes, void *stream);
+
+/* vec_dot without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same kernels and the same summation order as vec_dot,
+ * so the result is bitwise that of vec_dot on the same data.  The per-tile
+ * partials live in a library-owned array of 512 KiB of device memory per
+ * GPU (allocated with the library's code object, held until the process
+ * ends); its address on the current device is looked up on the first call
+ * there.  The call itself allocates nothing.
+ * n <= 134217728 (65536 partials of 2048 entries), else SEM_ERR_ARG with
+ * nothing enqueued.  The stream must belong to the current device (NULL:
+ * the current device's null stream).  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (different streams, or
+ * different host threads) race and must be serialised by the caller.
+ * Nothing in the array needs clearing between calls. */
+int vec_dot_noalloc(int64_t n, const double *x_dev, const double *y_dev, const double *wt_dev,
+                    double *out_dev, void *stream);
 
 /* Generic gather-scatter (the "gs" kernel of paper Sec. V-B: a loop over the
  * unique ids of shared nodes, and for each an inner loop over its copies) for

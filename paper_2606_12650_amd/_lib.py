@@ -31,7 +31,7 @@ EXPORTS = (
     "vec_axpy", "vec_dot_workspace_bytes", "vec_dot", "sem_export", "sem_last_error",
     "sem_ax_lowp", "sem_batch_workspace_bytes", "sem_batch_create", "sem_batch_set_tile",
     "sem_batch_add", "sem_batch_step", "sem_batch_poll", "sem_batch_remove", "sem_batch_destroy",
-    "sem_gs_csr_build", "sem_gs", "sem_rtc_build",
+    "sem_gs_csr_build", "sem_gs", "vec_dot_noalloc", "sem_rtc_build",
 )
 
 
@@ -90,6 +90,7 @@ def _declare(lib):
         "sem_batch_destroy": (ctypes.c_int, [vp]),
         "sem_gs_csr_build": (ctypes.c_int, [i64, vp, vp, i64, vp, i64, P(i32), P(i64)]),
         "sem_gs": (ctypes.c_int, [i32, vp, vp, i64, i64, vp, vp]),
+        "vec_dot_noalloc": (ctypes.c_int, [i64, vp, vp, vp, vp, vp]),
         "sem_rtc_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, P(sz)]),
     }
     for name, (res, args) in sig.items():

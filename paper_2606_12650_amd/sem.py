@@ -222,3 +222,17 @@ def vec_dot(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = None,
                                        ws.numel() * ws.element_size(), _stream(x.device)))
     return out
 
+
+def vec_dot_noalloc(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """``vec_dot_noalloc``: ``vec_dot`` with the library's own partials array
+    (no workspace; the output tensor is the caller's)."""
+    n = x.numel()
+    _check_vec(x, n, "x", x.device)
+    _check_vec(y, n, "y", x.device)
+    if wt is not None:
+        _check_vec(wt, n, "wt", x.device)
+    out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else out
+    L.check("vec_dot_noalloc", L.lib().vec_dot_noalloc(n, _ptr(x), _ptr(y), _ptr(wt), _ptr(out),
+                                                       _stream(x.device)))
+    return out

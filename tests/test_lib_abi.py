@@ -69,6 +69,12 @@ def test_argument_errors_return_codes_without_launching():
     assert lib.sem_nlocal(None) == -1
     assert lib.sem_destroy(None) == L.SEM_ERR_ARG
     assert lib.vec_dot_workspace_bytes(2049) == 16
+    # vec_dot_noalloc refuses negative and over-capacity lengths before any HIP call
+    assert lib.vec_dot_noalloc(-1, fake, fake, None, fake, None) == L.SEM_ERR_ARG
+    assert lib.vec_dot_noalloc(65536 * 2048 + 1, fake, fake, None, fake, None) == L.SEM_ERR_ARG
+    assert b"exceeds" in lib.sem_last_error()
+    assert lib.vec_dot_noalloc(4, None, fake, None, fake, None) == L.SEM_ERR_ARG
+    assert lib.vec_dot_noalloc(4, fake, fake, None, None, None) == L.SEM_ERR_ARG
 
 
 def test_batch_workspace_and_create_arguments_host_only():
