@@ -238,7 +238,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     pv[m] = ld_once(u + idx[m]);
     if (CG) {
       xv[m] = ld_once(x + idx[m]);
-      mv[m] = minv_at(minv, idx[m]);
+      mv[m] = minv_at(minv, r, idx[m]);
       rv[m] = ld_once(r + idx[m]);
     }
   }

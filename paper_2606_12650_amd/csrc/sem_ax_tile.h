@@ -77,7 +77,7 @@ __device__ __forceinline__ void ax_tile_col(int64_t E, int64_t e0, const typenam
         const int64_t idx = base + k * PL;
         const TV pold = ld_once(u + idx);
         st_once(x + idx, ld_once(x + idx) + alpha * pold);
-        const TV v = minv_at(minv, idx) * ld_once(r + idx) + beta * pold;
+        const TV v = minv_at(minv, r, idx) * ld_once(r + idx) + beta * pold;
         uk[k] = (TC)v;
         st_once(u + idx, v);
       }
@@ -262,7 +262,7 @@ __device__ __forceinline__ void ax_tile_split(int64_t E, int64_t e0, const typen
     pv[kk] = ld_once(u + idx[kk]);
     if (CG) {
       xv[kk] = ld_once(x + idx[kk]);
-      mv[kk] = minv_at(minv, idx[kk]);
+      mv[kk] = minv_at(minv, r, idx[kk]);
       rv[kk] = ld_once(r + idx[kk]);
     }
   }

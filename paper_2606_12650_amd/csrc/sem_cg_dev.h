@@ -136,7 +136,7 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
         r[idx] = rt;
         const double c = n.inv_mult();
         rr += c * rt * rt;
-        rz += c * rt * (minv_at(minv, idx) * rt);
+        rz += c * rt * (minv_at(minv, r, idx) * rt);
       }
     }
   }
@@ -247,7 +247,7 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
   for (int kk = 0; kk < KN; ++kk) {
     const int64_t a = p.col0 + (int64_t)min(p.kb + kk, N) * COLS;
     rv[kk] = (double)ld_once(r + a);
-    mv[kk] = (double)minv_at(minv, a);
+    mv[kk] = (double)minv_at(minv, r, a);
   }
   double S[KN];
   column_copy_sums<N1, TV>(p, w, sA, S);
