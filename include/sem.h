@@ -255,6 +255,37 @@ int sem_gs(int32_t n_rows, const int32_t *offsets_dev, const int32_t *ids_dev, i
            int64_t n, double *w_dev, void *stream);
 
 
+/* ------------------------------------------------- specialisation study
+ * The paper compares kernels whose run-time values (the order N in the
+ * Poisson operator, the work-group size of the streaming kernels, the
+ * unrolled in-group reduction) are fixed in the generated code with a HIP
+ * implementation that leaves them variable (Sec. VIII-B, Tab. hip_vs_hip).
+ * These entry points are that variable form of three kernels, for timing
+ * against sem_ax (SEM_AX_LOCAL), vec_axpy and vec_dot; the solver never
+ * calls them.  Same results up to rounding order.
+ *
+ * sem_ax_generic: w = A_L u (element-local, as sem_ax with SEM_AX_LOCAL)
+ * with one kernel for every order, N a kernel argument: the vector-ALU
+ * column mapping with run-time loop bounds and LDS tiles sized at launch.
+ * Orders 1..11 (else SEM_ERR_UNSUPPORTED); u != w, L-vectors of doubles. */
+int sem_ax_generic(sem_ctx *ctx, const double *u_dev, double *w_dev, void *stream);
+
+/* y <- alpha*x + y with the work-group size `block` (a power of two in
+ * [64, 1024], else SEM_ERR_ARG) chosen at launch, one entry per thread and
+ * grid-stride step. */
+int vec_axpy_generic(int64_t n, double alpha, const double *x_dev, double *y_dev, int block,
+                     void *stream);
+
+/* Device scratch vec_dot_generic needs for (n, block); 0 if invalid. */
+size_t vec_dot_generic_workspace_bytes(int64_t n, int block);
+
+/* *out_dev <- sum_i wt_i x_i y_i with the work-group size `block` chosen at
+ * launch and the in-group tree as a loop over halving strides (a barrier per
+ * level); two launches (partials, then one group over them).  Deterministic
+ * for fixed (n, block). */
+int vec_dot_generic(int64_t n, const double *x_dev, const double *y_dev, const double *wt_dev,
+                    double *out_dev, void *dev_ws, size_t ws_bytes, int block, void *stream);
+
 /* Copy a setup field (enum sem_field) into dst_dev, which must hold the size
  * listed with the field. */
 int sem_export(sem_ctx *ctx, int field, double *dst_dev, void *stream);

@@ -7,5 +7,5 @@ takes device memory and streams from PyTorch.
 
 from ._lib import LIB_PATH, SemError  # noqa: F401
 from .sem import (ASSEMBLED, LOCAL, MASKED, CgResult, SemOperator, mesh_desc,  # noqa: F401
-                  gs, gs_csr_build, vec_axpy, vec_dot, vec_dot_noalloc, vec_dot_workspace,
-                  workspace_bytes)
+                  gs, gs_csr_build, vec_axpy, vec_axpy_generic, vec_dot, vec_dot_generic,
+                  vec_dot_noalloc, vec_dot_workspace, workspace_bytes)

@@ -32,6 +32,7 @@ EXPORTS = (
     "sem_ax_lowp", "sem_batch_workspace_bytes", "sem_batch_create", "sem_batch_set_tile",
     "sem_batch_add", "sem_batch_step", "sem_batch_poll", "sem_batch_remove", "sem_batch_destroy",
     "sem_gs_csr_build", "sem_gs", "vec_dot_noalloc", "sem_rtc_build",
+    "sem_ax_generic", "vec_axpy_generic", "vec_dot_generic_workspace_bytes", "vec_dot_generic",
 )
 
 
@@ -92,6 +93,10 @@ def _declare(lib):
         "sem_gs": (ctypes.c_int, [i32, vp, vp, i64, i64, vp, vp]),
         "vec_dot_noalloc": (ctypes.c_int, [i64, vp, vp, vp, vp, vp]),
         "sem_rtc_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, P(sz)]),
+        "sem_ax_generic": (ctypes.c_int, [vp, vp, vp, vp]),
+        "vec_axpy_generic": (ctypes.c_int, [i64, dbl, vp, vp, ctypes.c_int, vp]),
+        "vec_dot_generic_workspace_bytes": (sz, [i64, ctypes.c_int]),
+        "vec_dot_generic": (ctypes.c_int, [i64, vp, vp, vp, vp, vp, sz, ctypes.c_int, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

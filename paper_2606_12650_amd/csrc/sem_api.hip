@@ -631,6 +631,49 @@ int vec_dot(int64_t n, const double *x, const double *y, const double *wt, doubl
   return SEM_OK;
 }
 
+// ------------------------------------------------- specialisation study
+namespace {
+bool generic_block_ok(int block) { return block >= 64 && block <= 1024 && (block & (block - 1)) == 0; }
+}  // namespace
+
+int sem_ax_generic(sem_ctx *ctx, const double *u, double *w, void *stream) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_ax_generic: null handle");
+  if (!u || !w) return fail(SEM_ERR_ARG, "sem_ax_generic: null vector");
+  if (u == w) return fail(SEM_ERR_ARG, "sem_ax_generic: u and w must differ");
+  if (ctx->box.N + 1 > semk::kGenericMaxN1)
+    return fail(SEM_ERR_UNSUPPORTED, "sem_ax_generic: orders above " + std::to_string(semk::kGenericMaxN1 - 1) +
+                                         " are not served by the run-time-order kernel");
+  SEM_HIP(semk::launch_ax_generic(ctx->box, ctx->D, ctx->G, u, w, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+int vec_axpy_generic(int64_t n, double alpha, const double *x, double *y, int block, void *stream) {
+  if (n < 0) return fail(SEM_ERR_ARG, "vec_axpy_generic: n < 0");
+  if (n > 0 && (!x || !y)) return fail(SEM_ERR_ARG, "vec_axpy_generic: null vector");
+  if (!generic_block_ok(block)) return fail(SEM_ERR_ARG, "vec_axpy_generic: block must be a power of two in [64, 1024]");
+  SEM_HIP(semk::launch_axpy_generic(n, alpha, x, y, block, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+size_t vec_dot_generic_workspace_bytes(int64_t n, int block) {
+  if (n < 0 || !generic_block_ok(block)) return 0;
+  return (size_t)semk::generic_dot_groups(n, block) * sizeof(double);
+}
+
+int vec_dot_generic(int64_t n, const double *x, const double *y, const double *wt, double *out,
+                    void *dev_ws, size_t ws_bytes, int block, void *stream) {
+  if (n < 0) return fail(SEM_ERR_ARG, "vec_dot_generic: n < 0");
+  if (n > 0 && (!x || !y)) return fail(SEM_ERR_ARG, "vec_dot_generic: null vector");
+  if (!out) return fail(SEM_ERR_ARG, "vec_dot_generic: null output");
+  if (!generic_block_ok(block)) return fail(SEM_ERR_ARG, "vec_dot_generic: block must be a power of two in [64, 1024]");
+  if (!dev_ws) return fail(SEM_ERR_ARG, "vec_dot_generic: null workspace");
+  if (((uintptr_t)dev_ws) % sizeof(double) != 0) return fail(SEM_ERR_ARG, "vec_dot_generic: workspace not 8-byte aligned");
+  if (ws_bytes < vec_dot_generic_workspace_bytes(n, block))
+    return fail(SEM_ERR_NOMEM, "vec_dot_generic: workspace too small");
+  SEM_HIP(semk::launch_dot_generic(n, x, y, wt, out, (double *)dev_ws, block, (hipStream_t)stream));
+  return SEM_OK;
+}
+
 int sem_export(sem_ctx *ctx, int field, double *dst, void *stream) {
   if (!ctx) return fail(SEM_ERR_ARG, "sem_export: null handle");
   if (!dst) return fail(SEM_ERR_ARG, "sem_export: null destination");

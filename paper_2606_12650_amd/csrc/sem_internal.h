@@ -94,6 +94,22 @@ hipError_t launch_outer_correct(const Box &b, double *x, float *e, const float *
 hipError_t launch_outer_step(const Box &b, const double *bvec, const double *w64, double *r64,
                              CgState *outer, double *part, hipStream_t s);
 
+// Non-specialised kernels of the specialisation study (sem_generic.hip):
+// the operator with N a run-time argument (orders 1..kGenericMaxN1 - 1),
+// axpy and dot with the work-group size `block` chosen at launch (a power of
+// two in [64, 1024]) and a looped in-group tree.  The dot's partials hold
+// generic_dot_groups(n, block) doubles.
+constexpr int kGenericMaxN1 = 12;
+constexpr int64_t kGenericMaxGrid = 65536;
+int generic_ax_epb(int N);
+int64_t generic_dot_groups(int64_t n, int block);
+hipError_t launch_ax_generic(const Box &b, const double *D, const double *G, const double *u,
+                             double *w, hipStream_t s);
+hipError_t launch_axpy_generic(int64_t n, double alpha, const double *x, double *y, int block,
+                               hipStream_t s);
+hipError_t launch_dot_generic(int64_t n, const double *x, const double *y, const double *wt,
+                              double *out, double *partials, int block, hipStream_t s);
+
 // Generic vectors.
 hipError_t launch_axpy(int64_t n, double alpha, const double *x, double *y, hipStream_t s);
 hipError_t launch_dot(int64_t n, const double *x, const double *y, const double *wt,

@@ -145,6 +145,15 @@ class SemOperator:
             L.check("sem_cg", rc)
         return x, res
 
+    def ax_generic(self, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """``sem_ax_generic``: w = A_L u with the run-time-order kernel (the
+        non-specialised form of the specialisation study)."""
+        _check_vec(u, self.L, "u", self.device)
+        w = self.empty() if out is None else out
+        _check_vec(w, self.L, "out", self.device)
+        L.check("sem_ax_generic", L.lib().sem_ax_generic(self._ctx, _ptr(u), _ptr(w), _stream(self.device)))
+        return w
+
     def export(self, field: int) -> torch.Tensor:
         """``sem_export``: a copy of a setup field."""
         n1 = self.n
@@ -234,5 +243,34 @@ def vec_dot_noalloc(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = 
         _check_vec(wt, n, "wt", x.device)
     out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else out
     L.check("vec_dot_noalloc", L.lib().vec_dot_noalloc(n, _ptr(x), _ptr(y), _ptr(wt), _ptr(out),
+                                                       _stream(x.device)))
+    return out
+
+
+def vec_axpy_generic(alpha: float, x: torch.Tensor, y: torch.Tensor, block: int = 256) -> torch.Tensor:
+    """``vec_axpy_generic``: y <- alpha x + y with the work-group size chosen at launch."""
+    n = y.numel()
+    _check_vec(x, n, "x", y.device)
+    _check_vec(y, n, "y", y.device)
+    L.check("vec_axpy_generic", L.lib().vec_axpy_generic(n, float(alpha), _ptr(x), _ptr(y), int(block),
+                                                         _stream(y.device)))
+    return y
+
+
+def vec_dot_generic(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = None,
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                    block: int = 256) -> torch.Tensor:
+    """``vec_dot_generic``: the dot with a run-time work-group size and a looped tree."""
+    n = x.numel()
+    _check_vec(x, n, "x", x.device)
+    _check_vec(y, n, "y", x.device)
+    if wt is not None:
+        _check_vec(wt, n, "wt", x.device)
+    out = torch.empty(1, dtype=torch.float64, device=x.device) if out is None else out
+    if ws is None:
+        nbytes = int(L.lib().vec_dot_generic_workspace_bytes(int(n), int(block)))
+        ws = torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=x.device)
+    L.check("vec_dot_generic", L.lib().vec_dot_generic(n, _ptr(x), _ptr(y), _ptr(wt), _ptr(out), _ptr(ws),
+                                                       ws.numel() * ws.element_size(), int(block),
                                                        _stream(x.device)))
     return out
