@@ -34,7 +34,8 @@ METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latenc
 
 def _kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h"):
+    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h",
+              "sem_kernels.h", "sem_types.h"):
         with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -44,7 +45,7 @@ def _cg_source_hash() -> str:
     """Hash of every source the CG iteration's kernels are built from."""
     h = hashlib.sha256()
     for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h",
-              "sem_cg_dev.h", "sem_vec.hip"):
+              "sem_kernels.h", "sem_types.h", "sem_cg_dev.h", "sem_vec.hip"):
         with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -63,6 +64,30 @@ def _traffic_from_profile(kernel_hash: str):
     return d.get("hbm_bytes_per_launch")
 
 
+MFMA_PROFILE = os.path.join(ROOT, "profiles", "mfma_e32768_counters.json")
+
+
+def _mfma_from_profile(kernel_hash: str, kernel: str):
+    """Matrix-core use of `kernel` (a substring of its name) from the committed
+    rocprofv3 counter run (MFMA ops and busy cycles), if it was taken on the
+    current kernel source; else None.  Keys: dtype, mfma_flops_per_launch,
+    achieved_tflops, peak_tflops, util (achieved / dense peak of the type),
+    busy_frac (MFMA-busy SIMD cycles / all SIMD cycles of the launch)."""
+    if not os.path.exists(MFMA_PROFILE):
+        return None
+    with open(MFMA_PROFILE) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    row = d.get("kernels", {}).get(kernel)
+    if not row or "util" not in row:
+        return None
+    dt = row["dtype"]
+    return {"dtype": dt, "mfma_flops_per_launch": row["mfma_flops_per_dispatch"][dt],
+            "achieved_tflops": row["achieved_tflops"], "peak_tflops": row["peak_tflops"],
+            "util": row["util"], "busy_frac": row["busy_frac"], "profiled_avg_us": row["avg_us"]}
+
+
 def _cg_traffic_frac(iters: int, wall: float):
     """HBM bytes the CG iterations actually moved (operator and update
     kernels, from the committed counter runs, while the kernel source is
@@ -77,8 +102,7 @@ def _cg_traffic_frac(iters: int, wall: float):
         return None
     per_iter = 0.0
     for name, v in d.get("all_kernels", {}).items():
-        if name.startswith("void semk::(anonymous namespace)::ax_mfma_kernel<8, semk::PrecF64, true>") or \
-                name.startswith("void semk::(anonymous namespace)::cg_update_kernel<8, double>"):
+        if "ax_mfma_kernel<8, semk::PrecF64, true>" in name or "cg_update_kernel<8, double>" in name:
             per_iter += v["hbm_bytes"]
     if per_iter == 0.0:
         return None
@@ -282,6 +306,10 @@ def bench_ax_study(args, dev, orders=(7, 11)) -> dict:
                                 "us": mean * 1e6, "best_run_us": best * 1e6,
                                 "gdofs": A.E * N ** 3 / mean / 1e9, "bytes_per_point": bpp,
                                 "gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+                    if mf:
+                        P = {"f64": "PrecF64", "f32": "PrecF32", "bf16": "PrecBF16"}[prec]
+                        row[key]["mfma"] = _mfma_from_profile(_kernel_source_hash(),
+                                                              f"ax_mfma_kernel<{N + 1}, semk::{P}, false>")
                     print(f"[bench] ax N={N} {key}: {row[key]}", file=sys.stderr, flush=True)
                     A.close()
                     del A, w
@@ -506,29 +534,67 @@ def bench_batching(args, dev) -> dict:
     return res
 
 
-def bench_serving(args, dev) -> dict:
+def bench_serving(args, dev, rates=None, n=None, warmup=None, budgets_gb=None) -> dict:
     """Poisson arrivals of solve requests (log-uniform E in [64, 32768], N in
-    {5,7,9}, tolerance 1e-8, 32 GB HBM budget): continuous batching with the
-    inner-outer FP32 solver vs one FP64 sem_cg per request."""
+    {5,7,9}, tolerance 1e-8; request seeds 5): continuous batching with the
+    inner-outer FP32 solver under an HBM budget vs one FP64 sem_cg per
+    request.  For each arrival rate: `n` timed requests after `warmup`
+    untimed ones (the percentiles and the throughput window cover the timed
+    ones), at each budget.  A rate is marked overload when it exceeds the
+    throughput the server reached at it (the queue then grows for the whole
+    run and the latencies measure its drain, not service time)."""
     import workload
     from paper_2606_12650_amd import serve as sv
 
+    rates = rates or [float(r) for r in args.serve_rates.split(",") if r]
+    n = args.serve_requests if n is None else n
+    warmup = args.serve_warmup if warmup is None else warmup
+    budgets_gb = budgets_gb or [32]
     out = {}
-    n = args.serve_requests
-    for rate in [float(r) for r in args.serve_rates.split(",") if r]:
-        specs = workload.serving_requests(5, n)
-        reqs = sv.make_requests(specs, workload.poisson_arrivals(5, rate, n))
-        st_b, _ = sv.serve(reqs, dev, mixed="f32", hbm_budget=32 << 30, max_slots=64, iters_per_step=20)
-        sb = st_b.summary()
+    for rate in rates:
+        specs = workload.serving_requests(5, n + warmup)
+        reqs = sv.make_requests(specs, workload.poisson_arrivals(5, rate, n + warmup))
+        row = {}
+        for gb in budgets_gb:
+            st_b, _ = sv.serve(reqs, dev, mixed="f32", hbm_budget=int(gb) << 30, max_slots=64, iters_per_step=20)
+            sb = st_b.summary(warmup)
+            sb["overload"] = rate > 1.1 * sb["solves_per_s"]
+            row["mixed_f32_continuous_batching" if gb == budgets_gb[0] else f"mixed_f32_budget_{gb}gb"] = sb
+            print(f"[bench] serving rate {rate} budget {gb} GB: batched {sb['solves_per_s']:.1f}/s "
+                  f"p50 {sb['p50_latency_s']:.2f}s p99 {sb['p99_latency_s']:.2f}s", file=sys.stderr, flush=True)
         st_p = sv.serve_per_request(reqs, dev)
-        sp = st_p.summary()
-        out[str(int(rate))] = {"mixed_f32_continuous_batching": sb, "fp64_per_request": sp,
-                               "solves_per_s_ratio": sb["solves_per_s"] / max(sp["solves_per_s"], 1e-12)}
+        sp = st_p.summary(warmup)
+        sp["overload"] = rate > 1.1 * sp["solves_per_s"]
+        sb = row["mixed_f32_continuous_batching"]
+        row["fp64_per_request"] = sp
+        row["solves_per_s_ratio"] = sb["solves_per_s"] / max(sp["solves_per_s"], 1e-12)
+        row["p99_ratio"] = sb["p99_latency_s"] / max(sp["p99_latency_s"], 1e-12)
+        out[f"{rate:g}"] = row
         print(f"[bench] serving rate {rate}: batched {sb['solves_per_s']:.1f}/s p99 {sb['p99_latency_s']:.2f}s, "
               f"per-request {sp['solves_per_s']:.1f}/s p99 {sp['p99_latency_s']:.2f}s", file=sys.stderr, flush=True)
     out["requests_per_rate"] = n
+    out["warmup_requests"] = warmup
+    out["hbm_budgets_gb"] = budgets_gb
     out["mesh_mix"] = "E log-uniform [64, 32768], N uniform {5,7,9}, amp 0.05, tol 1e-8"
     return out
+
+
+def serve_study(args) -> int:
+    """The serving protocol of the measurement plan: arrival rates 50, 100,
+    200, 500, 1000 and 2000 requests/s (all above one GPU's capacity of about
+    13 solves/s at this mix, so overload) plus rates below capacity, `n`
+    timed requests after `warmup`, HBM budgets 32 GB and a tighter one.
+    Prints one JSON line."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    rates = [float(r) for r in args.serve_study_rates.split(",") if r]
+    budgets = [int(b) for b in args.serve_study_budgets.split(",") if b]
+    res = bench_serving(args, dev, rates=rates, n=args.serve_requests, warmup=args.serve_warmup,
+                        budgets_gb=budgets)
+    print(json.dumps({"serve_study": res}), flush=True)
+    return 0
 
 
 def _box_for(E: int):
@@ -540,12 +606,55 @@ def _box_for(E: int):
     return dims[0], dims[1], dims[2]
 
 
+def _specialisation_ablation(A, b, nx, ny, nz, N, stream, reps: int) -> dict:
+    """The paper's HIP-fixed vs HIP-variable comparison (Sec. VIII-B,
+    Tab. hip_vs_hip) per kernel on this mesh: microseconds per call, mean of 5
+    graph-replayed runs of `reps` calls, of
+      ax:   the operator (element-local A_L u) with N fixed at compile time
+            (the vector-ALU column tile) vs the same mapping with N a
+            run-time argument (sem_ax_generic);
+      dot:  vec_dot (group size and unrolled tree fixed) vs vec_dot_generic
+            (group size 256 chosen at launch, looped tree), n = L;
+      axpy: vec_axpy (group size fixed) vs vec_axpy_generic (256 at launch).
+    ``speedup`` is generic time over fixed time."""
+    import torch
+
+    import paper_2606_12650_amd as sem
+
+    dev = b.device
+    Av = sem.SemOperator(nx, ny, nz, N, 0.05, device=dev, mfma=False)
+    w = torch.empty_like(b)
+    y = b.clone()
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = sem.vec_dot_workspace(A.L, dev)
+    nb = int(sem._lib.lib().vec_dot_generic_workspace_bytes(A.L, 256))
+    wsg = torch.empty(max(1, (nb + 7) // 8), dtype=torch.float64, device=dev)
+    pairs = {
+        "ax": (lambda: Av.ax(b, sem.LOCAL, out=w), lambda: Av.ax_generic(b, out=w)),
+        "dot": (lambda: sem.vec_dot(b, y, out=out, ws=ws),
+                lambda: sem.vec_dot_generic(b, y, out=out, ws=wsg, block=256)),
+        "axpy": (lambda: sem.vec_axpy(1e-3, b, y), lambda: sem.vec_axpy_generic(1e-3, b, y, block=256)),
+    }
+    res = {}
+    for name, (fixed, generic) in pairs.items():
+        tf, _ = _graph_time(fixed, reps, stream)
+        tg, _ = _graph_time(generic, reps, stream)
+        res[name] = {"fixed_us": tf * 1e6, "generic_us": tg * 1e6, "speedup": tg / tf}
+    Av.close()
+    return res
+
+
 def sweep(args) -> int:
     """GDOFS vs number of DOFs (the paper's Sec. VIII-B study, Eq. gdofs),
-    re-run on one MI355X with this library's Jacobi-PCG (FP64, deformed box):
-    for each N and E = 2^1..2^14, 100 warm-up iterations, then 100 timed
-    iterations, averaged over 5 runs.  One JSON line per (N, E), then one
-    summary line."""
+    re-run on one MI355X: for each N in {4, 6, 8} and E = 2^1..2^14 (balanced
+    power-of-two boxes, deformed), 100 warm-up CG iterations, then 100 timed
+    iterations, the time averaged over 5 runs.  The solver is the paper's
+    plain (unpreconditioned) CG of its Nekbone runs (Sec. VIII-A);
+    ``--sweep-pcg`` runs the Jacobi-PCG of the library's default instead.
+    Each row also holds the relative residual ||r||_c / ||b||_c after the 100
+    iterations, with a flag for the paper's 1e-7 .. 1e-6 band (Sec. VIII-C;
+    the paper's right-hand side is not ours, so the band is context, not a
+    pass mark).  One JSON line per (N, E), then one summary line."""
     import torch
 
     import workload
@@ -553,6 +662,7 @@ def sweep(args) -> int:
 
     dev = torch.device("cuda", 0)
     stream = torch.cuda.Stream(device=dev)
+    precond = bool(args.sweep_pcg)
     rows = []
     with torch.cuda.stream(stream):
         for N in (4, 6, 8):
@@ -561,23 +671,40 @@ def sweep(args) -> int:
                 A = sem.SemOperator(nx, ny, nz, N, 0.05, device=dev)
                 b = torch.from_numpy(workload.continuous_rhs(4, nx, ny, nz, N)).to(dev)
                 x = torch.empty_like(b)
-                A.cg(b, x, fixed_iter=100, check_every=100)  # warm-up (and graph capture)
+                A.cg(b, x, fixed_iter=100, check_every=100, precond=precond)  # warm-up (and graph capture)
                 times = []
                 for _ in range(5):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    _, res = A.cg(b, x, fixed_iter=100, check_every=100)
+                    _, res = A.cg(b, x, fixed_iter=100, check_every=100, precond=precond)
                     torch.cuda.synchronize()
                     times.append(time.perf_counter() - t0)
                 t = sum(times) / len(times)
                 E = nx * ny * nz
-                row = {"N": N, "E": E, "dofs": E * N ** 3, "unique_dofs": (nx * N + 1) * (ny * N + 1) * (nz * N + 1),
-                       "t_100_iters_s": t, "gdofs": E * N ** 3 * 100 / t / 1e9, "rel_res": res.rel_res}
+                row = {"N": N, "E": E, "box": [nx, ny, nz], "dofs": E * N ** 3,
+                       "unique_dofs": (nx * N + 1) * (ny * N + 1) * (nz * N + 1),
+                       "solver": "jacobi_pcg" if precond else "cg",
+                       "t_100_iters_s": t, "t_min_s": min(times), "gdofs": E * N ** 3 * 100 / t / 1e9,
+                       "rel_res_100": res.rel_res, "in_paper_band_1e-7_1e-6": 1e-7 <= res.rel_res <= 1e-6}
+                if not args.no_ablation:
+                    row["ablation"] = _specialisation_ablation(A, b, nx, ny, nz, N, stream, args.ax_reps)
                 rows.append(row)
                 print(json.dumps(row), flush=True)
                 A.close()
     best = {N: max(r["gdofs"] for r in rows if r["N"] == N) for N in (4, 6, 8)}
-    print(json.dumps({"sweep": "gdofs_vs_dofs", "max_gdofs": best}), flush=True)
+    sat = {}
+    for N in (4, 6, 8):
+        rs = [r for r in rows if r["N"] == N]
+        top = max(r["gdofs"] for r in rs)
+        first = next((r["dofs"] for r in rs if r["gdofs"] >= 0.9 * top), None)
+        sat[N] = first
+    summary = {"sweep": "gdofs_vs_dofs", "solver": "jacobi_pcg" if precond else "cg",
+               "max_gdofs": best, "dofs_at_90pct_of_max": sat}
+    if not args.no_ablation:
+        big = {N: max((r for r in rows if r["N"] == N), key=lambda r: r["E"]) for N in (4, 6, 8)}
+        summary["ablation_speedup_at_largest_E"] = {
+            N: {k: v["speedup"] for k, v in r["ablation"].items()} for N, r in big.items()}
+    print(json.dumps(summary), flush=True)
     return 0
 
 
@@ -601,13 +728,27 @@ def main(argv=None) -> int:
                     help="a short run of every kernel the profiles cover (for rocprofv3); prints its JSON")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=100)
-    ap.add_argument("--serve-rates", type=str, default="50,1000")
+    ap.add_argument("--serve-rates", type=str, default="5,50,1000",
+                    help="arrival rates (requests/s) of the serving study in the default run")
+    ap.add_argument("--serve-warmup", type=int, default=10,
+                    help="untimed requests before the timed ones at each rate")
+    ap.add_argument("--serve-study", action="store_true",
+                    help="only the serving protocol (--serve-study-rates, --serve-study-budgets, "
+                         "--serve-requests timed after --serve-warmup); prints its JSON")
+    ap.add_argument("--serve-study-rates", type=str, default="2,5,10,50,100,200,500,1000,2000")
+    ap.add_argument("--serve-study-budgets", type=str, default="32,8", help="HBM budgets in GB")
     ap.add_argument("--sweep", action="store_true",
                     help="the paper's study instead: GDOF/s vs DOFs for N = 4, 6, 8, E = 2^1..2^14, "
-                         "100 warm-up + 100 timed PCG iterations, mean of 5 runs")
+                         "100 warm-up + 100 timed plain CG iterations, mean of 5 runs")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="with --sweep: skip the fixed-vs-generic kernel timings")
+    ap.add_argument("--sweep-pcg", action="store_true",
+                    help="with --sweep: Jacobi-PCG instead of the paper's plain CG")
     args = ap.parse_args(argv)
     if args.sweep and args.gpus == 1:
         return sweep(args)
+    if args.serve_study and args.gpus == 1:
+        return serve_study(args)
     if (args.ax_only or args.profile_kernels) and args.gpus == 1:
         import torch
 
@@ -876,6 +1017,9 @@ def main(argv=None) -> int:
             "min_run_avg_launch_us": ax_s_min * 1e6,
             "launches_timed": 5 * args.ax_reps,
             "kernel_source_hash": khash,
+            # the D contractions on the matrix cores (f64 MFMA), from the
+            # committed counter run: not the bound, reported beside it
+            "mfma": _mfma_from_profile(khash, "ax_mfma_kernel<8, semk::PrecF64, false>"),
         },
     }
     if ax_study is not None:
