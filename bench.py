@@ -726,6 +726,10 @@ def main(argv=None) -> int:
                     help="only the A.u study; prints its JSON")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="a short run of every kernel the profiles cover (for rocprofv3); prints its JSON")
+    ap.add_argument("--skip-tune", action="store_true",
+                    help="skip the kernel-shape search of the single-solve CG (autotune.tune_solver)")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="only the kernel-shape search at N = 7 and 11; prints its JSON")
     ap.add_argument("--batch-instances", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--serve-rates", type=str, default="5,50,1000",
@@ -749,6 +753,15 @@ def main(argv=None) -> int:
         return sweep(args)
     if args.serve_study and args.gpus == 1:
         return serve_study(args)
+    if args.tune_only and args.gpus == 1:
+        import torch
+
+        from paper_2606_12650_amd import autotune
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"autotune_solver": autotune.tune_solver(orders=(7, 11), cache_path=None)}),
+              flush=True)
+        return 0
     if (args.ax_only or args.profile_kernels) and args.gpus == 1:
         import torch
 
@@ -955,6 +968,15 @@ def main(argv=None) -> int:
     ax_study = None if args.skip_ax_study else bench_ax_study(args, dev)
     c1 = None if args.skip_c1 else bench_c1(args, dev)
     precision_n11 = None if args.skip_n11 else bench_precision_order(args, dev, 11)
+    tuned = None
+    if not args.skip_tune:
+        from paper_2606_12650_amd import autotune
+
+        t0 = time.perf_counter()
+        tuned = autotune.tune_solver(orders=(7, 11), device=dev, cache_path=None)
+        print(f"[bench] kernel-shape search ({time.perf_counter() - t0:.1f} s): "
+              + "; ".join(f"{p} N={n}: op {r['op_tile']} update {r['update_tile']}"
+                          for p, d in tuned.items() for n, r in d.items()), file=sys.stderr, flush=True)
     batching = None if args.skip_batch else bench_batching(args, dev)
     serving = None if args.skip_serve else bench_serving(args, dev)
 
@@ -1028,6 +1050,11 @@ def main(argv=None) -> int:
         out["c1"] = c1
     if precision_n11 is not None:
         out["precision_n11"] = precision_n11
+    if tuned is not None:
+        # per (family, order): microseconds per CG iteration of every candidate
+        # element tile (1 matrix-core, 2 vector-ALU) and update tile shape
+        # (0 the default), and the chosen ones
+        out["autotune_solver"] = tuned
     if batching is not None:
         out["batching"] = batching
     if serving is not None:

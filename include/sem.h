@@ -255,6 +255,39 @@ int sem_gs(int32_t n_rows, const int32_t *offsets_dev, const int32_t *ids_dev, i
            int64_t n, double *w_dev, void *stream);
 
 
+/* ------------------------------------------------------------ kernel knobs
+ * Tuning hooks (the launch-shape choices the paper's transformation scripts
+ * make from the device context, Sec. V-B, Tab. context_params).  Each knob
+ * has candidates 0 .. sem_knob_count() - 1, all compiled with the library;
+ * 0 is the default (what measured fastest on MI355X).  They change the
+ * kernels a context runs, not what it computes: results agree up to the
+ * rounding order of the sums.
+ *   SEM_KNOB_OP_TILE      the element operator's tile: 0 default, 1 the
+ *                         matrix-core tile, 2 the vector-ALU tile (as
+ *                         sem_mesh_desc.flags, per precision family);
+ *   SEM_KNOB_UPDATE_TILE  the shape of the CG update tile (the gather-scatter
+ *                         fused into r -= alpha A p): threads per (i, j)
+ *                         column, elements per tile, plane ranges.
+ * `prec` names the family: SEM_F64 for the FP64 operator and update (sem_ax,
+ * the FP64 CG and the outer steps of the mixed one), SEM_F32 or SEM_BF16 for
+ * the inner operator and update of the mixed CG.  Orders 13..15 have the
+ * default only. */
+enum sem_knob { SEM_KNOB_OP_TILE = 0, SEM_KNOB_UPDATE_TILE = 1 };
+
+/* Number of candidates of `knob` for an order and precision family; 0 for
+ * an invalid combination.  Host only. */
+int sem_knob_count(int order, int prec, int knob);
+
+/* Select candidate `value` of `knob` for the family `prec` of ctx (SEM_F64,
+ * or ctx's low-precision copy).  The next sem_ax / sem_cg call runs it (a
+ * captured CG graph is dropped).  SEM_ERR_UNSUPPORTED for a value outside
+ * the candidates; SEM_ERR_ARG for a context in a batch (batches run the
+ * defaults, and sem_batch_add refuses a context with a knob set). */
+int sem_set_knob(sem_ctx *ctx, int prec, int knob, int value);
+
+/* The current value of a knob. */
+int sem_get_knob(const sem_ctx *ctx, int prec, int knob, int *value);
+
 /* ------------------------------------------------- specialisation study
  * The paper compares kernels whose run-time values (the order N in the
  * Poisson operator, the work-group size of the streaming kernels, the

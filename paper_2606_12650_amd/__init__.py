@@ -6,6 +6,7 @@ takes device memory and streams from PyTorch.
 """
 
 from ._lib import LIB_PATH, SemError  # noqa: F401
-from .sem import (ASSEMBLED, LOCAL, MASKED, CgResult, SemOperator, mesh_desc,  # noqa: F401
+from .sem import (ASSEMBLED, LOCAL, MASKED, OP_TILE, UPDATE_TILE, CgResult, SemOperator,  # noqa: F401
+                  knob_count, mesh_desc,
                   gs, gs_csr_build, vec_axpy, vec_axpy_generic, vec_dot, vec_dot_generic,
                   vec_dot_noalloc, vec_dot_workspace, workspace_bytes)

@@ -24,6 +24,7 @@ SEM_AX_LOCAL, SEM_AX_ASSEMBLED, SEM_AX_MASKED = 0, 1, 3
 SEM_FIELD_G, SEM_FIELD_MINV, SEM_FIELD_D, SEM_FIELD_NODES, SEM_FIELD_C = 0, 1, 2, 3, 4
 SEM_FLAG_MFMA, SEM_FLAG_VALU = 1, 2
 SEM_PRECOND_JACOBI, SEM_PRECOND_NONE = 0, 1
+SEM_KNOB_OP_TILE, SEM_KNOB_UPDATE_TILE = 0, 1
 
 # Every symbol include/sem.h declares.
 EXPORTS = (
@@ -33,6 +34,7 @@ EXPORTS = (
     "sem_batch_add", "sem_batch_step", "sem_batch_poll", "sem_batch_remove", "sem_batch_destroy",
     "sem_gs_csr_build", "sem_gs", "vec_dot_noalloc", "sem_rtc_build",
     "sem_ax_generic", "vec_axpy_generic", "vec_dot_generic_workspace_bytes", "vec_dot_generic",
+    "sem_knob_count", "sem_set_knob", "sem_get_knob",
 )
 
 
@@ -94,6 +96,9 @@ def _declare(lib):
         "vec_dot_noalloc": (ctypes.c_int, [i64, vp, vp, vp, vp, vp]),
         "sem_rtc_build": (ctypes.c_int, [ctypes.c_int, ctypes.c_char_p, P(sz)]),
         "sem_ax_generic": (ctypes.c_int, [vp, vp, vp, vp]),
+        "sem_knob_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "sem_set_knob": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "sem_get_knob": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, P(ctypes.c_int)]),
         "vec_axpy_generic": (ctypes.c_int, [i64, dbl, vp, vp, ctypes.c_int, vp]),
         "vec_dot_generic_workspace_bytes": (sz, [i64, ctypes.c_int]),
         "vec_dot_generic": (ctypes.c_int, [i64, vp, vp, vp, vp, vp, sz, ctypes.c_int, vp]),

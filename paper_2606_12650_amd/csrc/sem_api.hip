@@ -211,6 +211,10 @@ struct sem_ctx {
   CgState *st_in;
   // partial counts: elements, streaming tiles, FP64 and FP32 update tiles
   int64_t n_ax_blocks, n_vec_blocks, n_upd_blocks, n_upd_blocks_in;
+  // kernel variants (sem_set_knob): element tile (OpImpl) and update tile
+  // shape (upd_shape), [0] for the FP64 iterations, [1] for the inner ones
+  int op_impl[2];
+  int upd_var[2];
   CgState host_state;  // staging for the state upload / status reads
   CgState host_inner;
   int in_batch;  // 1 while the context is a slot of a batch
@@ -233,9 +237,9 @@ namespace {
 // one-group step for beta, the residual and the done flag.
 int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_f64(b, c->desc.flags, c->D, c->G, c->p, c->w, c->r, c->cg_minv, x, c->st, c->part_ax, s));
+  SEM_HIP(semk::launch_ax_f64(b, c->op_impl[0], c->D, c->G, c->p, c->w, c->r, c->cg_minv, x, c->st, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st, c->part_ax, c->n_ax_blocks, s));
-  SEM_HIP(semk::launch_cg_update(b, c->r, c->w, c->cg_minv, c->st, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_update(b, c->upd_var[0], c->r, c->w, c->cg_minv, c->st, c->part_rr, c->part_rz, s));
   SEM_HIP(semk::launch_cg_beta(c->st, c->part_rr, c->part_rz, c->n_upd_blocks, s));
   return SEM_OK;
 }
@@ -244,10 +248,11 @@ int enqueue_cg_iteration(sem_ctx *c, double *x, hipStream_t s) {
 // on FP32 vectors with the rounded operator; the inner correction e plays x.
 int enqueue_inner_iteration(sem_ctx *c, double *, hipStream_t s) {
   const Box &b = c->box;
-  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->desc.flags, c->Dlo, c->Glo,
+  SEM_HIP(semk::launch_ax_lowp(b, c->desc.lowprec, c->op_impl[1], c->Dlo, c->Glo,
                                c->pin, c->win, c->rin, c->minv32, c->e, c->st_in, c->part_ax, s));
   SEM_HIP(semk::launch_cg_alpha(c->st_in, c->part_ax, c->n_ax_blocks, s));
-  SEM_HIP(semk::launch_cg_update_f32(b, c->rin, c->win, c->minv32, c->st_in, c->part_rr, c->part_rz, s));
+  SEM_HIP(semk::launch_cg_update_f32(b, c->upd_var[1], c->rin, c->win, c->minv32, c->st_in, c->part_rr,
+                                     c->part_rz, s));
   SEM_HIP(semk::launch_cg_beta(c->st_in, c->part_rr, c->part_rz, c->n_upd_blocks_in, s));
   return SEM_OK;
 }
@@ -390,6 +395,8 @@ int sem_setup(const sem_mesh_desc *desc, void *dev_ws, size_t ws_bytes, void *st
   c->n_vec_blocks = semk::vec_grid_blocks(c->box.L());
   c->n_upd_blocks = semk::upd_num_tiles(c->box, true);
   c->n_upd_blocks_in = semk::upd_num_tiles(c->box, false);
+  c->op_impl[0] = c->op_impl[1] = desc->flags;
+  c->upd_var[0] = c->upd_var[1] = 0;
   c->in_batch = 0;
   for (int slot = 0; slot < 2; ++slot) {
     c->graph[slot] = nullptr;
@@ -468,12 +475,12 @@ int sem_ax(sem_ctx *ctx, const double *u, double *w, int mode, void *stream) {
     return fail(SEM_ERR_ARG, "sem_ax: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
   if (mode == SEM_AX_LOCAL) {
-    SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->desc.flags, ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
+    SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->op_impl[0], ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, s));
     return SEM_OK;
   }
   // element-local result into the workspace, then the gather-scatter pull
-  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->desc.flags, ctx->D, ctx->G, const_cast<double *>(u), ctx->w, nullptr,
+  SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->op_impl[0], ctx->D, ctx->G, const_cast<double *>(u), ctx->w, nullptr,
                               nullptr, nullptr, nullptr, nullptr, s));
   SEM_HIP(semk::launch_gather(ctx->box, ctx->w, w,
                               mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));
@@ -540,7 +547,7 @@ int sem_cg(sem_ctx *ctx, const double *b, double *x, const sem_cg_opts *opts, se
       if (rc != SEM_OK) return rc;
       inner_total += hi.iter;
       SEM_HIP(semk::launch_outer_correct(bx, x, ctx->e, ctx->pin, ctx->st_in, ctx->st, s));
-      SEM_HIP(semk::launch_ax_f64(bx, ctx->desc.flags, ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
+      SEM_HIP(semk::launch_ax_f64(bx, ctx->op_impl[0], ctx->D, ctx->G, x, ctx->w, nullptr, nullptr, nullptr, nullptr,
                                   nullptr, s));
       SEM_HIP(semk::launch_outer_step(bx, b, ctx->w, ctx->r, ctx->st, ctx->part_rr, s));
       SEM_HIP(hipMemcpyAsync(&h, ctx->st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -572,7 +579,7 @@ int sem_ax_lowp(sem_ctx *ctx, const float *u, float *w, int mode, void *stream) 
     return fail(SEM_ERR_ARG, "sem_ax_lowp: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
   float *dst = mode == SEM_AX_LOCAL ? w : ctx->win;
-  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->desc.flags, ctx->Dlo,
+  SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->op_impl[1], ctx->Dlo,
                                ctx->Glo, const_cast<float *>(u), dst, nullptr, nullptr, nullptr, nullptr,
                                nullptr, s));
   if (mode != SEM_AX_LOCAL)
@@ -628,6 +635,60 @@ int vec_dot(int64_t n, const double *x, const double *y, const double *wt, doubl
   if (((uintptr_t)dev_ws) % sizeof(double) != 0) return fail(SEM_ERR_ARG, "vec_dot: workspace not 8-byte aligned");
   if (ws_bytes < vec_dot_workspace_bytes(n)) return fail(SEM_ERR_NOMEM, "vec_dot: workspace too small");
   SEM_HIP(semk::launch_dot(n, x, y, wt, out, (double *)dev_ws, (hipStream_t)stream));
+  return SEM_OK;
+}
+
+// ------------------------------------------------------------ kernel knobs
+namespace {
+// Candidates of a knob for an order and precision family (0 when invalid).
+int knob_count(int order, int prec, int knob) {
+  if (order < semk::kMinOrder || order > semk::kMaxRtcOrder) return 0;
+  if (prec != SEM_F64 && prec != SEM_F32 && prec != SEM_BF16) return 0;
+  if (semk::rtc_order(order)) return (prec == SEM_F64 && (knob == SEM_KNOB_OP_TILE || knob == SEM_KNOB_UPDATE_TILE)) ? 1 : 0;
+  if (knob == SEM_KNOB_OP_TILE) return 3;
+  if (knob == SEM_KNOB_UPDATE_TILE) {
+    int n = 0;
+    while (n < semk::kUpdVariants && semk::upd_variant_exists(order + 1, prec == SEM_F64, n)) ++n;
+    return n;
+  }
+  return 0;
+}
+}  // namespace
+
+int sem_knob_count(int order, int prec, int knob) { return knob_count(order, prec, knob); }
+
+int sem_set_knob(sem_ctx *ctx, int prec, int knob, int value) {
+  if (!ctx) return fail(SEM_ERR_ARG, "sem_set_knob: null handle");
+  if (ctx->in_batch) return fail(SEM_ERR_ARG, "sem_set_knob: the context is a slot of a batch");
+  if (prec != SEM_F64 && prec != ctx->desc.lowprec)
+    return fail(SEM_ERR_ARG, "sem_set_knob: prec must be SEM_F64 or the context's low-precision copy");
+  if (knob != SEM_KNOB_OP_TILE && knob != SEM_KNOB_UPDATE_TILE)
+    return fail(SEM_ERR_ARG, "sem_set_knob: knob must be SEM_KNOB_OP_TILE or SEM_KNOB_UPDATE_TILE");
+  const int n = knob_count(ctx->box.N, prec, knob);
+  if (value < 0 || value >= n)
+    return fail(SEM_ERR_UNSUPPORTED, "sem_set_knob: value " + std::to_string(value) + " outside the " +
+                                         std::to_string(n) + " candidates of this order and precision");
+  const int fam = prec == SEM_F64 ? 0 : 1;
+  if (knob == SEM_KNOB_OP_TILE) {
+    ctx->op_impl[fam] = value;
+  } else {
+    ctx->upd_var[fam] = value;
+    if (fam == 0) ctx->n_upd_blocks = semk::upd_num_tiles(ctx->box, true, value);
+    else ctx->n_upd_blocks_in = semk::upd_num_tiles(ctx->box, false, value);
+  }
+  drop_graph(ctx, 0);  // captured iterations hold the old kernels
+  drop_graph(ctx, 1);
+  return SEM_OK;
+}
+
+int sem_get_knob(const sem_ctx *ctx, int prec, int knob, int *value) {
+  if (!ctx || !value) return fail(SEM_ERR_ARG, "sem_get_knob: null argument");
+  if (prec != SEM_F64 && prec != ctx->desc.lowprec)
+    return fail(SEM_ERR_ARG, "sem_get_knob: prec must be SEM_F64 or the context's low-precision copy");
+  const int fam = prec == SEM_F64 ? 0 : 1;
+  if (knob == SEM_KNOB_OP_TILE) *value = ctx->op_impl[fam];
+  else if (knob == SEM_KNOB_UPDATE_TILE) *value = ctx->upd_var[fam];
+  else return fail(SEM_ERR_ARG, "sem_get_knob: knob must be SEM_KNOB_OP_TILE or SEM_KNOB_UPDATE_TILE");
   return SEM_OK;
 }
 
@@ -847,8 +908,9 @@ int sem_batch_add(sem_batch *B, sem_ctx *ctx, const double *b, double *x, const 
   if (opts->mixed && ctx->desc.lowprec == SEM_F64)
     return fail(SEM_ERR_ARG, "sem_batch_add: mixed precision needs a low-precision copy");
   if (ctx->box.N > 11) return fail(SEM_ERR_UNSUPPORTED, "sem_batch_add: batches take orders 1..11");
-  if (ctx->desc.flags != 0)
-    return fail(SEM_ERR_ARG, "sem_batch_add: batches run the default element kernels (flags must be 0)");
+  if (ctx->desc.flags != 0 || ctx->op_impl[0] != 0 || ctx->op_impl[1] != 0 || ctx->upd_var[0] != 0 ||
+      ctx->upd_var[1] != 0)
+    return fail(SEM_ERR_ARG, "sem_batch_add: batches run the default kernels (flags 0, no knob set)");
   int q = -1;
   for (int i = 0; i < B->max_slots; ++i)
     if (!B->ctx[i]) {

@@ -69,15 +69,18 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
 // The work-group has BLOCK threads; tid is threadIdx.x.  LINEAR tiles (FP64
 // from order 9) take kVecTile consecutive entries instead, each node summing
 // its copies in ascending element-local order with missing copies masked.
-template <int N1, typename TV>
+// V selects one of the candidate shapes of upd_shape (0: the default).
+template <int N1, typename TV, int V = 0>
 struct UpdTile {
-  static constexpr bool LINEAR = upd_linear(N1, sizeof(TV) == 8);
+  static constexpr UpdShape SH = upd_shape(N1, sizeof(TV) == 8, V);
+  static_assert(SH.ks >= 0, "update tile shape not among the candidates of this order");
+  static constexpr bool LINEAR = SH.ks == 0;
   static constexpr int N = N1 - 1;
   static constexpr int COLS = N1 * N1;
   static constexpr int NP = COLS * N1;
-  static constexpr int KS = upd_ks(N1, sizeof(TV) == 8);  // threads per column
-  static constexpr int EPT = upd_ept(N1, sizeof(TV) == 8);  // elements per tile
-  static constexpr int KP = upd_kp(N1, sizeof(TV) == 8);  // tiles per element (plane ranges)
+  static constexpr int KS = LINEAR ? 1 : SH.ks;    // threads per column
+  static constexpr int EPT = LINEAR ? 1 : SH.ept;  // elements per tile
+  static constexpr int KP = LINEAR ? 1 : SH.kp;    // tiles per element (plane ranges)
   static constexpr int KT = (N1 + KP - 1) / KP;  // planes per tile
   static constexpr int KN = (KT + KS - 1) / KS;  // planes per thread
   static constexpr int THREADS = EPT * KS * COLS;
@@ -147,15 +150,17 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
 }
 
 // Where a thread of an element-column tile sits: its element, its (i, j)
-// column, its planes kb .. kb + KN - 1 and the copies its nodes have.
-template <int N1, typename TV>
+// column, its planes kb .. kb + KN - 1 (those below kend are its own: the
+// last thread of a plane range can reach past it when KS does not divide the
+// range) and the copies its nodes have.
+template <int N1, typename TV, int V = 0>
 struct ColumnPos {
-  using U = UpdTile<N1, TV>;
+  using U = UpdTile<N1, TV, V>;
   static constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
   bool live, hy, z_lo, z_hi, hx, x_in;
-  int el, ks, col, i, j, kb, ex, ey, ez;
+  int el, ks, col, i, j, kb, kend, ex, ey, ez;
   int64_t yoff, dz, col0;
-  __device__ ColumnPos(const Box &b, int64_t tile, int tid) {
+  __host__ __device__ ColumnPos(const Box &b, int64_t tile, int tid) {
     const bool act = tid < U::THREADS;
     const int t = act ? tid : 0;
     el = t / (U::KS * COLS);
@@ -165,7 +170,9 @@ struct ColumnPos {
     i = col % N1;
     j = col / N1;
     const int64_t grp = tile / U::KP;
-    kb = (int)(tile - grp * U::KP) * U::KT + ks * KN;
+    const int part = (int)(tile - grp * U::KP);
+    kb = part * U::KT + ks * KN;
+    kend = (part + 1) * U::KT < N1 ? (part + 1) * U::KT : N1;
     const int64_t E = b.E();
     const int64_t e_raw = grp * U::EPT + el;
     live = act && e_raw < E;
@@ -186,12 +193,12 @@ struct ColumnPos {
     col0 = (int64_t)e * NP + col;
   }
   // Plane k (of this thread) is a node on the box boundary.
-  __device__ bool boundary(const Box &b, int k) const {
+  __host__ __device__ bool boundary(const Box &b, int k) const {
     return (i == 0 && ex == 0) || (i == N && ex == b.nx - 1) || (j == 0 && ey == 0) ||
            (j == N && ey == b.ny - 1) || (k == 0 && ez == 0) || (k == N && ez == b.nz - 1);
   }
   // 1 / multiplicity of the node at plane k.
-  __device__ double inv_mult(const Box &b, int k) const {
+  __host__ __device__ double inv_mult(const Box &b, int k) const {
     const bool hz = (k == 0 && ez > 0) || (k == N && ez < b.nz - 1);
     const int m = (hx ? 2 : 1) * (hy ? 2 : 1) * (hz ? 2 : 1);
     return m == 1 ? 1.0 : (m == 2 ? 0.5 : (m == 4 ? 0.25 : 0.125));
@@ -201,10 +208,10 @@ struct ColumnPos {
 // S = the sum of all copies of each of the thread's nodes, as the pair tree
 // above.  With several elements per tile this holds a work-group barrier:
 // every thread of the work-group calls it.
-template <int N1, typename TV>
-__device__ inline void column_copy_sums(const ColumnPos<N1, TV> &p, const TV *__restrict__ w,
-                                        double *sA, double (&S)[UpdTile<N1, TV>::KN]) {
-  using U = UpdTile<N1, TV>;
+template <int N1, typename TV, int V = 0>
+__device__ inline void column_copy_sums(const ColumnPos<N1, TV, V> &p, const TV *__restrict__ w,
+                                        double *sA, double (&S)[UpdTile<N1, TV, V>::KN]) {
+  using U = UpdTile<N1, TV, V>;
   constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
   double A[KN];
   upd_column<N1, KN, TV>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, A);
@@ -232,16 +239,16 @@ __device__ inline void column_copy_sums(const ColumnPos<N1, TV> &p, const TV *__
   for (int kk = 0; kk < KN; ++kk) S[kk] = p.hx ? A[kk] + X[kk] : A[kk];
 }
 
-template <int N1, typename TV>
+template <int N1, typename TV, int V = 0>
 __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__restrict__ r,
                                           const TV *__restrict__ w, const TV *__restrict__ minv,
                                           double alpha, double *sA, double *sred,
                                           int tid) {
-  using U = UpdTile<N1, TV>;
+  using U = UpdTile<N1, TV, V>;
   if constexpr (U::LINEAR)
     return cg_update_tile_linear<N1>(b, tile, r, w, minv, alpha, sred, tid);
   constexpr int N = U::N, COLS = U::COLS, KN = U::KN;
-  const ColumnPos<N1, TV> p(b, tile, tid);
+  const ColumnPos<N1, TV, V> p(b, tile, tid);
   double rv[KN], mv[KN];
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
@@ -250,12 +257,12 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
     mv[kk] = (double)minv_at(minv, r, a);
   }
   double S[KN];
-  column_copy_sums<N1, TV>(p, w, sA, S);
+  column_copy_sums<N1, TV, V>(p, w, sA, S);
   double rr = 0.0, rz = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     const int k = p.kb + kk;
-    if (p.live && k <= N && !p.boundary(b, k)) {
+    if (p.live && k < p.kend && !p.boundary(b, k)) {
       const TV rt = (TV)(rv[kk] - alpha * S[kk]);
       r[p.col0 + (int64_t)k * COLS] = rt;
       const double c = p.inv_mult(b, k);

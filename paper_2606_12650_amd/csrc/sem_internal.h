@@ -65,8 +65,10 @@ hipError_t launch_cg_init(const Box &b, const double *bvec, double *x, double *r
                           const double *minv, CgState *st, double *part_a, double *part_b,
                           hipStream_t s);
 // CG update with the gather of w fused in: r -= alpha mask o QQ^T w,
-// partials of ||r||_c^2 and <r, Minv r>_c.  Skipped when done.
-hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
+// partials of ||r||_c^2 and <r, Minv r>_c (upd_num_tiles(b, f64, variant) of
+// each).  Skipped when done.  variant: the update tile shape (upd_shape; the
+// orders compiled at run time have shape 0 only).
+hipError_t launch_cg_update(const Box &b, int variant, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s);
 // One-group launches that finish the reductions and advance the scalars:
 // alpha = rho / <p, A p> (breakdown check), and after the update
@@ -78,7 +80,7 @@ hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,
                             hipStream_t s);
 // FP32 update for the inner solver of the inner-outer CG.
-hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
+hipError_t launch_cg_update_f32(const Box &b, int variant, float *r, const float *w, const float *minv,
                                 CgState *st, double *part_rr, double *part_rz, hipStream_t s);
 
 // Inner-outer CG steps.  inner_start: r_in = r / ||r||_c in FP32, e = p = 0,

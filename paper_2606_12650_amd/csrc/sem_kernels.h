@@ -248,7 +248,7 @@ __global__ void __launch_bounds__((UpdTile<N1, T>::BLOCK))
 #pragma unroll
   for (int kk = 0; kk < U::KN; ++kk) {
     const int k = p.kb + kk;
-    if (p.live && k <= U::N) {
+    if (p.live && k < p.kend) {
       double v = S[kk];
       if (MODE != kGatherAssembled && p.boundary(b, k))
         v = 0.0;
@@ -276,18 +276,20 @@ __global__ void __launch_bounds__(kVecThreads)
   }
 }
 
-template <int N1, typename TV>
-__global__ void __launch_bounds__((UpdTile<N1, TV>::BLOCK))
+// V: the update tile shape (upd_shape), one kernel per candidate.
+template <int N1, typename TV, int V = 0>
+__global__ void __launch_bounds__((UpdTile<N1, TV, V>::BLOCK))
     cg_update_kernel(Box b, int64_t ntiles, TV *__restrict__ r, const TV *__restrict__ w,
                      const TV *__restrict__ minv, CgState *__restrict__ st,
                      double *__restrict__ part_rr, double *__restrict__ part_rz) {
-  __shared__ double sred[UpdTile<N1, TV>::BLOCK / 64];
-  __shared__ double sA[UpdTile<N1, TV>::LDS];
+  __shared__ double sred[UpdTile<N1, TV, V>::BLOCK / 64];
+  __shared__ double sA[UpdTile<N1, TV, V>::LDS];
   if (st->done) return;
   const double alpha = st->alpha;
   const int64_t tile = xcd_tile(ntiles);
   TileSums t{0.0, 0.0};
-  if (tile < ntiles) t = cg_update_tile<N1, TV>(b, tile, r, w, minv, alpha, sA, sred, (int)threadIdx.x);
+  if (tile < ntiles)
+    t = cg_update_tile<N1, TV, V>(b, tile, r, w, minv, alpha, sA, sred, (int)threadIdx.x);
   if (threadIdx.x == 0) {
     part_rr[tile] = t.a;
     part_rz[tile] = t.b;

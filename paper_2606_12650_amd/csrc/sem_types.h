@@ -102,22 +102,72 @@ __host__ __device__ constexpr int upd_kp(int n1, bool f64) {
   return (n1 >= 13 || (f64 && n1 == 12)) ? 2 : 1;
 }
 __host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
-inline int64_t upd_num_tiles(const Box &b, bool f64) {
-  const int n1 = b.N + 1;
-  if (upd_linear(n1, f64)) return vec_num_blocks(b.L());
-  const int ept = upd_ept(n1, f64);
-  return (b.E() + ept - 1) / ept * upd_kp(n1, f64);
+
+// Candidate update tiles for tuning: shape v of an order and vector type
+// (threads per column, elements per tile, plane ranges per element).  v = 0
+// is the default above ({0, 0, 0}: the linear streaming tile); v = 1 ..
+// kUpdVariants - 1 are alternatives compiled beside it for orders 1..12:
+// more elements per tile, more threads per column (fewer planes per thread),
+// fewer elements per tile, or plane ranges.  Every candidate stays within
+// 512 threads and 32 KiB of LDS.  ks = -1 marks a missing candidate (the
+// orders compiled at run time have the default only).
+struct UpdShape {
+  int ks, ept, kp;
+};
+constexpr int kUpdVariants = 4;
+__host__ __device__ constexpr UpdShape upd_shape(int n1, bool f64, int v) {
+  if (v == 0)
+    return upd_linear(n1, f64) ? UpdShape{0, 0, 0} : UpdShape{upd_ks(n1, f64), upd_ept(n1, f64), upd_kp(n1, f64)};
+  if (v < 0 || v >= kUpdVariants) return UpdShape{-1, 0, 0};
+  switch (n1) {
+    case 2: return v == 1 ? UpdShape{1, 128, 1} : v == 2 ? UpdShape{1, 32, 1} : UpdShape{2, 32, 1};
+    case 3: return v == 1 ? UpdShape{1, 56, 1} : v == 2 ? UpdShape{1, 14, 1} : UpdShape{3, 18, 1};
+    case 4: return v == 1 ? UpdShape{1, 32, 1} : v == 2 ? UpdShape{1, 8, 1} : UpdShape{2, 16, 1};
+    case 5: return v == 1 ? UpdShape{1, 20, 1} : v == 2 ? UpdShape{1, 5, 1} : UpdShape{2, 10, 1};
+    case 6: return v == 1 ? UpdShape{1, 14, 1} : v == 2 ? UpdShape{2, 3, 1} : UpdShape{2, 7, 1};
+    case 7: return v == 1 ? UpdShape{1, 10, 1} : v == 2 ? UpdShape{2, 2, 1} : UpdShape{2, 5, 1};
+    case 8: return v == 1 ? UpdShape{1, 8, 1} : v == 2 ? UpdShape{2, 2, 1} : UpdShape{2, 4, 1};
+    case 9:
+      if (f64) return v == 1 ? UpdShape{1, 4, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{3, 1, 1};
+      return v == 1 ? UpdShape{1, 4, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{3, 2, 1};
+    case 10:
+      if (f64) return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{1, 4, 1};
+      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{1, 4, 1};
+    case 11:
+      if (f64) return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{1, 2, 1};
+      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{4, 1, 1};
+    case 12:
+      if (f64) return v == 1 ? UpdShape{1, 2, 2} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{3, 1, 1};
+      return v == 1 ? UpdShape{3, 1, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{2, 1, 2};
+    case 13:
+      if (f64) return v == 1 ? UpdShape{1, 2, 2} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{3, 1, 1};
+      return v == 1 ? UpdShape{2, 1, 1} : v == 2 ? UpdShape{3, 1, 1} : UpdShape{2, 1, 2};
+    default: return UpdShape{-1, 0, 0};
+  }
+}
+__host__ __device__ constexpr bool upd_variant_exists(int n1, bool f64, int v) {
+  return v >= 0 && v < kUpdVariants && upd_shape(n1, f64, v).ks >= 0;
+}
+// Update tiles of shape v on box b (one partial per tile).
+inline int64_t upd_num_tiles(const Box &b, bool f64, int v = 0) {
+  const UpdShape sh = upd_shape(b.N + 1, f64, v);
+  if (sh.ks == 0) return vec_num_blocks(b.L());
+  return (b.E() + sh.ept - 1) / sh.ept * sh.kp;
 }
 // Launch size of the update (a multiple of the XCD count).
-inline int64_t upd_grid_blocks(const Box &b, bool f64) {
-  return 8 * ((upd_num_tiles(b, f64) + 7) / 8);
+inline int64_t upd_grid_blocks(const Box &b, bool f64, int v = 0) {
+  return 8 * ((upd_num_tiles(b, f64, v) + 7) / 8);
 }
-// Partials a solve's streaming reductions need room for.
+// Partials a solve's streaming reductions need room for (every candidate
+// update tile of both vector types).
 inline int64_t stream_partials(const Box &b) {
   int64_t v = vec_grid_blocks(b.L());
-  const int64_t u64 = upd_grid_blocks(b, true), u32 = upd_grid_blocks(b, false);
-  if (u64 > v) v = u64;
-  if (u32 > v) v = u32;
+  for (int f = 0; f < 2; ++f)
+    for (int k = 0; k < kUpdVariants; ++k)
+      if (upd_variant_exists(b.N + 1, f == 1, k)) {
+        const int64_t u = upd_grid_blocks(b, f == 1, k);
+        if (u > v) v = u;
+      }
   return v;
 }
 

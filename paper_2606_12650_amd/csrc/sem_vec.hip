@@ -187,27 +187,43 @@ __global__ void __launch_bounds__(kFinThreads)
 
 inline dim3 vec_grid(int64_t n) { return dim3((unsigned)vec_num_blocks(n)); }
 
+// The update of order N1 - 1 with tile shape V (upd_shape).
+template <int N1, typename TV, int V>
+hipError_t update_launch(const Box &b, TV *r, const TV *w, const TV *minv, CgState *st,
+                         double *part_rr, double *part_rz, hipStream_t s) {
+  constexpr bool f64 = sizeof(TV) == 8;
+  if constexpr (!upd_variant_exists(N1, f64, V)) {
+    return hipErrorInvalidValue;
+  } else {
+    hipLaunchKernelGGL((cg_update_kernel<N1, TV, V>), dim3((unsigned)upd_grid_blocks(b, f64, V)),
+                       dim3(UpdTile<N1, TV, V>::BLOCK), 0, s, b, upd_num_tiles(b, f64, V), r, w,
+                       minv, st, part_rr, part_rz);
+    return hipGetLastError();
+  }
+}
+
 template <typename TV>
-hipError_t update_typed(const Box &b, TV *r, const TV *w, const TV *minv, CgState *st,
+hipError_t update_typed(const Box &b, int variant, TV *r, const TV *w, const TV *minv, CgState *st,
                         double *part_rr, double *part_rz, hipStream_t s) {
   if (b.E() == 0) return hipSuccess;
-  const bool f64 = sizeof(TV) == 8;
-  const int64_t nt = upd_num_tiles(b, f64);
-  const dim3 grid((unsigned)upd_grid_blocks(b, f64));
   switch (b.N) {
-#define UCASE(n_)                                                                        \
-  case n_:                                                                               \
-    hipLaunchKernelGGL((cg_update_kernel<n_ + 1, TV>), grid, dim3(UpdTile<n_ + 1, TV>::BLOCK), 0, \
-                       s, b, nt, r, w, minv, st, part_rr, part_rz);                      \
-    break;
+#define UCASE(n_)                                                                                \
+  case n_:                                                                                       \
+    switch (variant) {                                                                           \
+      case 0: return update_launch<n_ + 1, TV, 0>(b, r, w, minv, st, part_rr, part_rz, s);       \
+      case 1: return update_launch<n_ + 1, TV, 1>(b, r, w, minv, st, part_rr, part_rz, s);       \
+      case 2: return update_launch<n_ + 1, TV, 2>(b, r, w, minv, st, part_rr, part_rz, s);       \
+      case 3: return update_launch<n_ + 1, TV, 3>(b, r, w, minv, st, part_rr, part_rz, s);       \
+      default: return hipErrorInvalidValue;                                                      \
+    }
     UCASE(1) UCASE(2) UCASE(3) UCASE(4) UCASE(5) UCASE(6)
     UCASE(7) UCASE(8) UCASE(9) UCASE(10) UCASE(11) UCASE(12)
 #undef UCASE
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
+static_assert(kUpdVariants == 4, "update_typed dispatches four candidate shapes");
 inline dim3 xcd_vec_grid(int64_t n) { return dim3((unsigned)vec_grid_blocks(n)); }
 
 }  // namespace
@@ -320,15 +336,18 @@ hipError_t launch_cg_beta(CgState *st, const double *part_rr, const double *part
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const Box &b, double *r, const double *w, const double *minv,
+hipError_t launch_cg_update(const Box &b, int variant, double *r, const double *w, const double *minv,
                             CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  if (rtc_order(b.N)) return b.E() == 0 ? hipSuccess : rtc_cg_update(b, r, w, minv, st, part_rr, part_rz, s);
-  return update_typed<double>(b, r, w, minv, st, part_rr, part_rz, s);
+  if (rtc_order(b.N)) {
+    if (variant != 0) return hipErrorInvalidValue;
+    return b.E() == 0 ? hipSuccess : rtc_cg_update(b, r, w, minv, st, part_rr, part_rz, s);
+  }
+  return update_typed<double>(b, variant, r, w, minv, st, part_rr, part_rz, s);
 }
 
-hipError_t launch_cg_update_f32(const Box &b, float *r, const float *w, const float *minv,
+hipError_t launch_cg_update_f32(const Box &b, int variant, float *r, const float *w, const float *minv,
                                 CgState *st, double *part_rr, double *part_rz, hipStream_t s) {
-  return update_typed<float>(b, r, w, minv, st, part_rr, part_rz, s);
+  return update_typed<float>(b, variant, r, w, minv, st, part_rr, part_rz, s);
 }
 
 hipError_t launch_cg_finish(const Box &b, double *x, const double *p, const CgState *st,

@@ -145,6 +145,17 @@ class SemOperator:
             L.check("sem_cg", rc)
         return x, res
 
+    def set_knob(self, knob: int, value: int, prec: str = "f64") -> None:
+        """``sem_set_knob``: kernel variant `value` of `knob` (``OP_TILE`` or
+        ``UPDATE_TILE``) for the FP64 family (``prec="f64"``) or the inner
+        low-precision one (the context's ``lowprec``)."""
+        L.check("sem_set_knob", L.lib().sem_set_knob(self._ctx, _PREC[prec], int(knob), int(value)))
+
+    def get_knob(self, knob: int, prec: str = "f64") -> int:
+        v = ctypes.c_int(0)
+        L.check("sem_get_knob", L.lib().sem_get_knob(self._ctx, _PREC[prec], int(knob), ctypes.byref(v)))
+        return v.value
+
     def ax_generic(self, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """``sem_ax_generic``: w = A_L u with the run-time-order kernel (the
         non-specialised form of the specialisation study)."""
@@ -274,3 +285,11 @@ def vec_dot_generic(x: torch.Tensor, y: torch.Tensor, wt: torch.Tensor | None = 
                                                        ws.numel() * ws.element_size(), int(block),
                                                        _stream(x.device)))
     return out
+
+
+OP_TILE, UPDATE_TILE = L.SEM_KNOB_OP_TILE, L.SEM_KNOB_UPDATE_TILE
+
+
+def knob_count(order: int, knob: int, prec: str = "f64") -> int:
+    """``sem_knob_count``: candidates of a knob for an order and precision family."""
+    return int(L.lib().sem_knob_count(int(order), _PREC[prec], int(knob)))
