@@ -75,7 +75,7 @@ struct ClassPrec<3> {
 template <int N1, int EPB, bool MFMA>
 struct OpCfg {
   static constexpr int THREADS =
-      MFMA ? 64 * MfmaTile<N1>::NT * EPB : (AxTile<N1>::TPE * EPB + 63) / 64 * 64;
+      MFMA ? 64 * MfmaTile<N1>::W * EPB : (AxTile<N1>::TPE * EPB + 63) / 64 * 64;
   static constexpr int kTiles = MFMA ? 3 : AxTile<N1>::kTiles;
   static constexpr int SRED = MFMA ? THREADS / 64 : THREADS;
 };
@@ -380,7 +380,7 @@ template <int N1, bool MIXED>
 __global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
     batch_upd_kernel(const BatchSlot *__restrict__ slots, BatchSched sc, int list) {
   using TV = typename std::conditional<MIXED, float, double>::type;
-  __shared__ double sred[BatchUpd<N1, MIXED>::BLOCK / 64];
+  __shared__ double sred[2 * (BatchUpd<N1, MIXED>::BLOCK / 64)];
   __shared__ double sA[BatchUpd<N1, MIXED>::LDS];
   const int cnt = sc.meta[2 * list], total = sc.meta[2 * list + 1];
   int w0, w1;
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__((BatchUpd<N1, MIXED>::BLOCK))
 // The outer steps' true residuals of the mixed solves (every order).
 __global__ void __launch_bounds__(kVecThreads)
     batch_resid_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   walk_list(slots, sc, kBatchResidList, [&](const BatchSlot &S, int tile) {
     switch (S.N) {
 #define RCASE(n_) \
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kVecThreads)
 template <bool MIXED>
 __global__ void __launch_bounds__(kVecThreads)
     batch_fin_kernel(const BatchSlot *__restrict__ slots, BatchSched sc) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   walk_list(slots, sc, kBatchFinList + (MIXED ? 1 : 0), [&](const BatchSlot &S, int tile) {
     switch (S.N) {
 #define FCASE(n_) \
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(kVecThreads)
 // Per-solve launches: one work-group of kFinThreads per slot.
 __global__ void __launch_bounds__(kFinThreads)
     batch_alpha_kernel(const BatchSlot *__restrict__ slots) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   const BatchSlot &S = slots[blockIdx.x];
   if (!S.active) return;
   if (S.mixed == 0 && S.phase == kPhaseFp64)
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(kFinThreads)
 
 __global__ void __launch_bounds__(kFinThreads)
     batch_beta_kernel(BatchSlot *__restrict__ slots) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   BatchSlot &S = slots[blockIdx.x];
   if (!S.active) return;
   const int phase = S.phase;
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kFinThreads)
 
 __global__ void __launch_bounds__(kFinThreads)
     batch_phase_kernel(BatchSlot *__restrict__ slots, BatchStatus *__restrict__ status) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   BatchSlot &S = slots[blockIdx.x];
   if (!S.active) return;
   const int phase = S.phase;
@@ -617,8 +617,8 @@ bool launch_op(int cls, const BatchGrids &g, const BatchSlot *slots, const Batch
 int batch_default_epb(int cls, int N) {
   const int n1 = N + 1;
   if (op_uses_mfma(cls, N)) {
-    const int nt = (n1 * n1 + 15) / 16;
-    return nt >= 8 ? 1 : 8 / nt;
+    const int nw = mfma_waves(n1);
+    return nw >= 8 ? 1 : 8 / nw;
   }
   return n1 * n1 >= 128 ? 1 : 128 / (n1 * n1);
 }

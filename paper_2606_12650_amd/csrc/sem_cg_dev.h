@@ -46,8 +46,7 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
     }
   }
   TileSums t;
-  t.a = block_sum<kVecThreads>(rz, sred);
-  t.b = block_sum<kVecThreads>(bb, sred);
+  block_sum2<kVecThreads>(rz, bb, sred, &t.a, &t.b);
   return t;
 }
 
@@ -92,25 +91,25 @@ struct UpdTile {
 };
 
 // The A values (y and z pairs) of planes kb .. kb + KN - 1 of the column at
-// w + col0 (the address of its plane 0).
-template <int N1, int KN, typename TV>
+// w + col0 (the address of its plane 0), added in type AT.
+template <int N1, int KN, typename TV, typename AT = double>
 __device__ __forceinline__ void upd_column(const TV *__restrict__ w, int64_t col0, int kb,
                                            bool hy, int64_t yoff, bool z_lo, bool z_hi,
-                                           int64_t dz, double (&A)[KN]) {
+                                           int64_t dz, AT (&A)[KN]) {
   constexpr int N = N1 - 1, COLS = N1 * N1;
-  double own[KN], yv[KN];
+  AT own[KN], yv[KN];
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     const int64_t a = col0 + (int64_t)min(kb + kk, N) * COLS;
-    own[kk] = (double)w[a];
-    yv[kk] = (double)w[hy ? a + yoff : a];
+    own[kk] = (AT)w[a];
+    yv[kk] = (AT)w[hy ? a + yoff : a];
   }
   const int64_t lo = col0 - dz + (int64_t)N * COLS, hi = col0 + dz;
-  const double zl = (double)w[z_lo ? lo : col0];
-  const double zyl = (double)w[z_lo && hy ? lo + yoff : col0];
-  const double zh = (double)w[z_hi ? hi : col0];
-  const double zyh = (double)w[z_hi && hy ? hi + yoff : col0];
-  const double pl = hy ? zl + zyl : zl, ph = hy ? zh + zyh : zh;
+  const AT zl = (AT)w[z_lo ? lo : col0];
+  const AT zyl = (AT)w[z_lo && hy ? lo + yoff : col0];
+  const AT zh = (AT)w[z_hi ? hi : col0];
+  const AT zyh = (AT)w[z_hi && hy ? hi + yoff : col0];
+  const AT pl = hy ? zl + zyl : zl, ph = hy ? zh + zyh : zh;
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     A[kk] = hy ? own[kk] + yv[kk] : own[kk];
@@ -144,8 +143,7 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
     }
   }
   TileSums t;
-  t.a = block_sum<kVecThreads>(rr, sred);
-  t.b = block_sum<kVecThreads>(rz, sred);
+  block_sum2<kVecThreads>(rr, rz, sred, &t.a, &t.b);
   return t;
 }
 
@@ -206,33 +204,35 @@ struct ColumnPos {
 };
 
 // S = the sum of all copies of each of the thread's nodes, as the pair tree
-// above.  With several elements per tile this holds a work-group barrier:
-// every thread of the work-group calls it.
-template <int N1, typename TV, int V = 0>
+// above, added in type AT (the pairs and their order are the same in any
+// type, so every copy of a node gets the same bits).  With several elements
+// per tile this holds a work-group barrier: every thread of the work-group
+// calls it.
+template <int N1, typename TV, int V = 0, typename AT = double>
 __device__ inline void column_copy_sums(const ColumnPos<N1, TV, V> &p, const TV *__restrict__ w,
-                                        double *sA, double (&S)[UpdTile<N1, TV, V>::KN]) {
+                                        double *sA, AT (&S)[UpdTile<N1, TV, V>::KN]) {
   using U = UpdTile<N1, TV, V>;
   constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
-  double A[KN];
-  upd_column<N1, KN, TV>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, A);
-  double X[KN];
+  AT A[KN];
+  upd_column<N1, KN, TV, AT>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, A);
+  AT X[KN];
 #pragma unroll
-  for (int kk = 0; kk < KN; ++kk) X[kk] = 0.0;
+  for (int kk = 0; kk < KN; ++kk) X[kk] = (AT)0;
   if (p.hx && !p.x_in) {
     // the x copy column lies in the neighbouring element of another tile
     const int64_t xc = p.i == 0 ? p.col0 - NP + N : p.col0 + NP - N;
-    upd_column<N1, KN, TV>(w, xc, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, X);
+    upd_column<N1, KN, TV, AT>(w, xc, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, X);
   }
   if constexpr (U::EPT > 1) {
     // slot (element, thread's plane range, plane, column)
 #pragma unroll
-    for (int kk = 0; kk < KN; ++kk) sA[((p.el * U::KS + p.ks) * KN + kk) * COLS + p.col] = A[kk];
+    for (int kk = 0; kk < KN; ++kk) sA[((p.el * U::KS + p.ks) * KN + kk) * COLS + p.col] = (double)A[kk];
     __syncthreads();
     if (p.x_in) {
       const int xo =
           ((p.i == 0 ? p.el - 1 : p.el + 1) * U::KS + p.ks) * KN * COLS + p.j * N1 + (N - p.i);
 #pragma unroll
-      for (int kk = 0; kk < KN; ++kk) X[kk] = sA[xo + kk * COLS];
+      for (int kk = 0; kk < KN; ++kk) X[kk] = (AT)sA[xo + kk * COLS];  // exact: an AT value
     }
   }
 #pragma unroll
@@ -249,31 +249,33 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
     return cg_update_tile_linear<N1>(b, tile, r, w, minv, alpha, sred, tid);
   constexpr int N = U::N, COLS = U::COLS, KN = U::KN;
   const ColumnPos<N1, TV, V> p(b, tile, tid);
-  double rv[KN], mv[KN];
+  // the copies of w are summed, and r updated, in the vector type (FP64, or
+  // FP32 in the inner solve of the mixed CG); the reductions in FP64
+  TV rv[KN], mv[KN];
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     const int64_t a = p.col0 + (int64_t)min(p.kb + kk, N) * COLS;
-    rv[kk] = (double)ld_once(r + a);
-    mv[kk] = (double)minv_at(minv, r, a);
+    rv[kk] = ld_once(r + a);
+    mv[kk] = minv_at(minv, r, a);
   }
-  double S[KN];
-  column_copy_sums<N1, TV, V>(p, w, sA, S);
+  TV S[KN];
+  column_copy_sums<N1, TV, V, TV>(p, w, sA, S);
+  const TV alpha_v = (TV)alpha;
   double rr = 0.0, rz = 0.0;
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     const int k = p.kb + kk;
     if (p.live && k < p.kend && !p.boundary(b, k)) {
-      const TV rt = (TV)(rv[kk] - alpha * S[kk]);
+      const TV rt = rv[kk] - alpha_v * S[kk];
       r[p.col0 + (int64_t)k * COLS] = rt;
       const double c = p.inv_mult(b, k);
       const double rd = (double)rt;
       rr += c * rd * rd;
-      rz += c * rd * (mv[kk] * rd);
+      rz += c * rd * ((double)mv[kk] * rd);
     }
   }
   TileSums ts;
-  ts.a = block_sum<U::BLOCK>(rr, sred);
-  ts.b = block_sum<U::BLOCK>(rz, sred);
+  block_sum2<U::BLOCK>(rr, rz, sred, &ts.a, &ts.b);
   return ts;
 }
 
@@ -302,8 +304,7 @@ __device__ inline TileSums inner_start_tile(const Box &b, int64_t L, int64_t til
     }
   }
   TileSums t;
-  t.a = block_sum<kVecThreads>(rz, sred);
-  t.b = block_sum<kVecThreads>(rr, sred);
+  block_sum2<kVecThreads>(rz, rr, sred, &t.a, &t.b);
   return t;
 }
 
@@ -355,8 +356,8 @@ __device__ inline void outer_correct_tile(int64_t L, int64_t tile, double *__res
 // rho, ||b||_c and the tolerance after cg_init_tile.
 __device__ inline void cg_init_step(CgState *st, const double *__restrict__ part_rz,
                                     const double *__restrict__ part_bb, int64_t n, double *sred) {
-  const double rho = sum_partials<kFinThreads>(part_rz, n, sred);
-  const double bn = sum_partials<kFinThreads>(part_bb, n, sred);
+  double rho, bn;
+  sum_partials2<kFinThreads>(part_rz, part_bb, n, sred, &rho, &bn);
   if (threadIdx.x == 0) {
     st->rho = rho;
     st->bnorm2 = bn;
@@ -396,8 +397,8 @@ __device__ inline void cg_beta_step(CgState *st, const double *__restrict__ part
   const int it = st->iter + 1;
   const int max_iter = st->max_iter;
   const double rho = st->rho, tol2 = st->tol2;
-  const double rrt = sum_partials<kFinThreads>(part_rr, n, sred);
-  const double rzt = sum_partials<kFinThreads>(part_rz, n, sred);
+  double rrt, rzt;
+  sum_partials2<kFinThreads>(part_rr, part_rz, n, sred, &rrt, &rzt);
   if (threadIdx.x == 0 && done == kRunning) {
     st->iter = it;
     st->rnorm2 = rrt;
@@ -441,8 +442,8 @@ __device__ inline void outer_finish_step(CgState *st, const double *__restrict__
 __device__ inline void inner_init_step(CgState *st, const double *__restrict__ part_rz,
                                        const double *__restrict__ part_rr, int64_t n, double rtol2,
                                        int max_iter, double *sred) {
-  const double rho = sum_partials<kFinThreads>(part_rz, n, sred);
-  const double rr = sum_partials<kFinThreads>(part_rr, n, sred);
+  double rho, rr;
+  sum_partials2<kFinThreads>(part_rz, part_rr, n, sred, &rho, &rr);
   if (threadIdx.x == 0) {
     st->max_iter = max_iter;
     st->rtol2 = rtol2;

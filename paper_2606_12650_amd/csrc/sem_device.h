@@ -130,6 +130,32 @@ __device__ inline double block_sum(double v, double *sred) {
   return t;
 }
 
+// Two block sums in one pass (one barrier instead of two), each value in the
+// order of block_sum, so each result has block_sum's bits.  sred holds
+// 2 * T / 64 doubles.  Valid in thread 0.
+template <int T>
+__device__ inline void block_sum2(double a, double b, double *sred, double *ta, double *tb) {
+  static_assert(T % 64 == 0, "block size must be a multiple of the wave size");
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sred[wid] = a;
+    sred[T / 64 + wid] = b;
+  }
+  __syncthreads();
+  double x = 0.0, y = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < T / 64; ++q) x += sred[q];
+#pragma unroll
+    for (int q = 0; q < T / 64; ++q) y += sred[T / 64 + q];
+  }
+  __syncthreads();
+  *ta = x;
+  *tb = y;
+}
+
 constexpr int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -180,6 +206,45 @@ __device__ inline double sum_partials(const double *__restrict__ part, int64_t n
   }
   const double t = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum<T>(t, sred);
+}
+
+// sum_partials of two arrays of n partials at once: the loads of both are
+// issued together (two rounds of eight per array and thread), so the pair
+// waits for memory once.  Each array is summed in the order of sum_partials
+// (a running sum per residue of the index modulo 8 T, in ascending index,
+// however many rounds a pass holds), so each result has its bits.  sred
+// holds 2 * T / 64 doubles.  Valid in thread 0.
+template <int T>
+__device__ inline void sum_partials2(const double *__restrict__ pa, const double *__restrict__ pb,
+                                     int64_t n, double *sred, double *ta, double *tb) {
+  constexpr int R = 2;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double c[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = threadIdx.x; q < n; q += (int64_t)R * 8 * T) {
+    const int64_t q0 = q - threadIdx.x;
+    const int64_t left = (n - q0 + 8 * T - 1) / (8 * T);
+    const int rounds = left < R ? (int)left : R;
+    double va[R][8], vb[R][8];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t idx = q + (int64_t)(r * 8 + u) * T;
+        const bool ok = r < rounds && idx < n;
+        va[r][u] = ok ? pa[idx] : 0.0;
+        vb[r][u] = ok ? pb[idx] : 0.0;
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a[u] += va[r][u];
+        c[u] += vb[r][u];
+      }
+  }
+  const double x = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  const double y = ((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7]));
+  block_sum2<T>(x, y, sred, ta, tb);
 }
 
 // Work-groups are dispatched round-robin over the 8 XCDs; this maps the

@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(kVecThreads)
                    double *__restrict__ x, double *__restrict__ r, double *__restrict__ p,
                    const double *__restrict__ minv, double *__restrict__ part_rz,
                    double *__restrict__ part_bb) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   const int64_t tile = xcd_tile(ntiles);
   TileSums t{0.0, 0.0};
   if (tile < ntiles) t = cg_init_tile<N1>(b, L, tile, bvec, x, r, p, minv, sred);
@@ -282,7 +282,7 @@ __global__ void __launch_bounds__((UpdTile<N1, TV, V>::BLOCK))
     cg_update_kernel(Box b, int64_t ntiles, TV *__restrict__ r, const TV *__restrict__ w,
                      const TV *__restrict__ minv, CgState *__restrict__ st,
                      double *__restrict__ part_rr, double *__restrict__ part_rz) {
-  __shared__ double sred[UpdTile<N1, TV, V>::BLOCK / 64];
+  __shared__ double sred[2 * (UpdTile<N1, TV, V>::BLOCK / 64)];
   __shared__ double sA[UpdTile<N1, TV, V>::LDS];
   if (st->done) return;
   const double alpha = st->alpha;

@@ -27,26 +27,26 @@ namespace {
 __global__ void __launch_bounds__(kFinThreads)
     cg_init_finish_kernel(CgState *st, const double *__restrict__ part_rz,
                           const double *__restrict__ part_bb, int64_t n) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   cg_init_step(st, part_rz, part_bb, n, sred);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_alpha_kernel(CgState *st, const double *__restrict__ part, int64_t n) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   cg_alpha_step(st, part, n, sred);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
     cg_beta_kernel(CgState *st, const double *__restrict__ part_rr,
                    const double *__restrict__ part_rz, int64_t n) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   cg_beta_step(st, part_rr, part_rz, n, sred);
 }
 
 __global__ void __launch_bounds__(kFinThreads)
     outer_finish_kernel(CgState *st, const double *__restrict__ part, int64_t n) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   outer_finish_step(st, part, n, sred);
 }
 
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(kVecThreads)
                        float *__restrict__ e, float *__restrict__ p,
                        const float *__restrict__ minv32, double *__restrict__ part_rz,
                        double *__restrict__ part_rr) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   const double inv_s = 1.0 / sqrt(outer->rnorm2);
   const int64_t tile = xcd_tile(ntiles);
   TileSums t{0.0, 0.0};
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kVecThreads)
 __global__ void __launch_bounds__(kFinThreads)
     inner_init_kernel(CgState *st, const double *__restrict__ part_rz,
                       const double *__restrict__ part_rr, int64_t n, double rtol2, int max_iter) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   inner_init_step(st, part_rz, part_rr, n, rtol2, max_iter, sred);
 }
 
@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kVecThreads)
     residual_kernel(Box b, int64_t L, int64_t ntiles, const double *__restrict__ bvec,
                     const double *__restrict__ wl, double *__restrict__ r,
                     const CgState *__restrict__ outer, double *__restrict__ part) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   const int done = outer->done;
   const int64_t tile = xcd_tile(ntiles);
   double rr = 0.0;
@@ -147,7 +147,7 @@ template <bool W>
 __global__ void __launch_bounds__(kVecThreads)
     dot_partial_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                        const double *__restrict__ wt, double *__restrict__ part) {
-  __shared__ double sred[kVecThreads / 64];
+  __shared__ double sred[2 * (kVecThreads / 64)];
   const int64_t base = (int64_t)blockIdx.x * kVecTile + threadIdx.x;
   double acc = 0.0;
   if ((int64_t)(blockIdx.x + 1) * kVecTile <= n) {
@@ -180,7 +180,7 @@ __global__ void __launch_bounds__(kVecThreads)
 
 __global__ void __launch_bounds__(kFinThreads)
     dot_final_kernel(const double *__restrict__ part, int64_t n, double *__restrict__ out) {
-  __shared__ double sred[kFinThreads / 64];
+  __shared__ double sred[2 * (kFinThreads / 64)];
   const double t = sum_partials<kFinThreads>(part, n, sred);
   if (threadIdx.x == 0) *out = t;
 }
