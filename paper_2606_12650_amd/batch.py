@@ -31,8 +31,9 @@ def default_epb(order: int, prec: str = "f64") -> int:
     of the element kernel that order and precision run by default)."""
     n1 = order + 1
     if order >= {"f64": 7, "f32": 7, "bf16": 9}[prec]:  # matrix-core tile
-        nt = (n1 * n1 + 15) // 16
-        return 1 if nt >= 8 else 8 // nt
+        nt = (n1 * n1 + 15) // 16  # column tiles; waves per element: a multiple of four above two
+        nw = nt if nt <= 2 else (16 if nt > 8 else (nt + 3) // 4 * 4)
+        return 1 if nw >= 8 else 8 // nw
     return 1 if n1 * n1 >= 128 else 128 // (n1 * n1)
 
 

@@ -9,7 +9,9 @@
 // output 1-D index (N+1 of the 16 MFMA rows) and n a pair of the two other
 // indices: N+1 squared pairs in column tiles of 16.  An element has
 // ceil((N+1)^2 / 16) waves; wave w of an element takes column tile w of all
-// three directions.
+// three directions.  The element's waves are its column tiles rounded up to
+// a multiple of four, or 16 (mfma_waves); the waves beyond the last tile take
+// no part in the matrix-core phases but share the element's loads and stores.
 //
 // HBM loads and stores run in a flat layout (64 consecutive nodes per wave
 // and instruction); the MFMA results go through three LDS tiles.  Per
@@ -42,22 +44,37 @@ typedef double mfma_v4d __attribute__((ext_vector_type(4)));
 typedef float mfma_v4f __attribute__((ext_vector_type(4)));
 typedef short mfma_v4s __attribute__((ext_vector_type(4)));
 
+// Waves per element: the column tiles, rounded up to a multiple of four
+// above two, and 16 above eight.  A work-group's waves are spread over a CU's
+// four SIMDs; with nine waves (N = 11) one SIMD held three of each group, so
+// at seven waves per SIMD only two groups fit (measured: 14 of 27 possible
+// waves resident per CU).  With a multiple of four every SIMD holds the same
+// share; 16 waves at N = 11 also leave two nodes per thread instead of three
+// in the flat layout.  Measured at N = 11 (32^3 box): FP32 / BF16 CG operator
+// 529 / 482 -> 475 / 419 us, A.u 364 / 334 -> 336 / 296 us; FP64 unchanged.
+__host__ __device__ constexpr int mfma_waves(int n1) {
+  return ((n1 * n1 + 15) / 16) <= 2 ? (n1 * n1 + 15) / 16
+         : ((n1 * n1 + 15) / 16) > 8 ? 16
+                                      : ((n1 * n1 + 15) / 16 + 3) / 4 * 4;
+}
+
 template <int N1>
 struct MfmaTile {
   static_assert(N1 <= 16, "one MFMA row block per 1-D index");
   static constexpr int PL = N1 * N1;
-  static constexpr int NT = (PL + 15) / 16;  // column tiles = waves per element
+  static constexpr int NT = (PL + 15) / 16;  // column tiles
+  static constexpr int W = mfma_waves(N1);   // waves per element (>= NT)
   static constexpr int KS = (N1 + 3) / 4;    // 16x16x4 steps
   static constexpr int kTiles = 3;           // LDS tiles per element: U, R, S
 };
 
-// Work-group of the matrix-core operator: EPB elements of NT waves each
-// (about eight waves per work-group).
+// Work-group of the matrix-core operator: EPB elements of W waves each
+// (at least eight waves per work-group).
 template <int N1>
 struct MfmaCfg {
-  static constexpr int NT = MfmaTile<N1>::NT;
-  static constexpr int EPB = NT >= 8 ? 1 : 8 / NT;
-  static constexpr int THREADS = 64 * NT * EPB;
+  static constexpr int W = MfmaTile<N1>::W;
+  static constexpr int EPB = W >= 8 ? 1 : 8 / W;
+  static constexpr int THREADS = 64 * W * EPB;
 };
 
 template <class P>
@@ -200,12 +217,13 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   using Acc = typename MfmaOps<P>::Acc;
   constexpr int NP = T::NP;
   constexpr int PL = M::PL;
-  constexpr int NTT = 64 * M::NT;              // threads per element
+  constexpr int NTT = 64 * M::W;               // threads per element
   constexpr int PPT = (NP + NTT - 1) / NTT;    // nodes per thread in the flat layout
   const int tid = OPQ ? opaque_tid() : (int)threadIdx.x;
   const int wave = tid >> 6;
-  const int el = wave / M::NT;
-  const int tile = wave - el * M::NT;  // this wave's column tile in every direction
+  const int el = wave / M::W;
+  const int tile = wave - el * M::W;  // this wave's column tile in every direction
+  const bool tiled = tile < M::NT;    // (the waves beyond the last tile have none)
   const int l = tid & 63;
   const int lt = tid - el * NTT;       // thread index within the element
   const int64_t e = e0 + el;
@@ -279,7 +297,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   MfmaA<N1, P> A;
   A.load(sD, false, l);
   Acc ut = {0, 0, 0, 0};
-  if (mine) {
+  if (mine && tiled) {
     const Acc ur = mfma_contract<N1, P>(A, U, 0, tile, l);
     const Acc us = mfma_contract<N1, P>(A, U, 1, tile, l);
     ut = mfma_contract<N1, P>(A, U, 2, tile, l);
@@ -287,7 +305,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     mfma_store<N1, P>(S, us, 1, tile, l);
   }
   __syncthreads();  // every wave has read the operand tile
-  if (mine) mfma_store<N1, P>(U, ut, 2, tile, l);
+  if (mine && tiled) mfma_store<N1, P>(U, ut, 2, tile, l);
   if constexpr (LATE_G) load_gk();
   __syncthreads();
 
@@ -310,7 +328,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
   // divergence, in place: each wave reads and writes only its own column
   // tile's pairs in R (r), S (s) and U (t)
   A.load(sD, true, l);
-  if (mine) {
+  if (mine && tiled) {
     const Acc vr = mfma_contract<N1, P>(A, R, 0, tile, l);
     const Acc vs = mfma_contract<N1, P>(A, S, 1, tile, l);
     const Acc vt = mfma_contract<N1, P>(A, U, 2, tile, l);
@@ -339,7 +357,7 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
     __syncthreads();
     if (mine && tile == 0 && l == 0 && e < E) {
       double sum = 0.0;
-      for (int t = 0; t < M::NT; ++t) sum += sred[el * M::NT + t];
+      for (int t = 0; t < M::W; ++t) sum += sred[el * M::W + t];
       part_el[e] = sum;
     }
   }
