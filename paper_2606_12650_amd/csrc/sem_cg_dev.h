@@ -63,8 +63,8 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
 // Each pair is one commutative addition of the same two numbers for every
 // copy of the node (a missing copy leaves the other operand alone), so all
 // copies get the same bits.  The A of the x copy column comes from LDS when
-// that column is in the tile and is recomputed from w otherwise.  Missing
-// copies' loads are clamped to the node itself, so the loads carry no branch.
+// that column is in the tile and is recomputed from w otherwise.  A missing
+// copy is not loaded and adds an exact zero.
 // The work-group has BLOCK threads; tid is threadIdx.x.  LINEAR tiles (FP64
 // from order 9) take kVecTile consecutive entries instead, each node summing
 // its copies in ascending element-local order with missing copies masked.
@@ -90,33 +90,56 @@ struct UpdTile {
   static_assert(8 * LDS <= 32 * 1024, "update tile LDS above 32 KiB");
 };
 
-// The A values (y and z pairs) of planes kb .. kb + KN - 1 of the column at
-// w + col0 (the address of its plane 0), added in type AT.
-template <int N1, int KN, typename TV, typename AT = double>
-__device__ __forceinline__ void upd_column(const TV *__restrict__ w, int64_t col0, int kb,
-                                           bool hy, int64_t yoff, bool z_lo, bool z_hi,
-                                           int64_t dz, AT (&A)[KN]) {
+// The w values a column's pair sums read: its planes kb .. kb + KN - 1 (own),
+// their y copies and the z neighbours of planes 0 and N (with their y
+// copies).  A copy the node does not have is not loaded and reads as zero
+// (its lane's load is switched off, so it costs no memory request).
+template <int KN, typename TV>
+struct ColumnW {
+  TV own[KN], yv[KN];
+  TV zl, zyl, zh, zyh;
+};
+
+template <int N1, int KN, typename TV>
+__device__ __forceinline__ void upd_column_load(const TV *__restrict__ w, int64_t col0, int kb,
+                                                bool hy, int64_t yoff, bool z_lo, bool z_hi,
+                                                int64_t dz, ColumnW<KN, TV> &c) {
   constexpr int N = N1 - 1, COLS = N1 * N1;
-  AT own[KN], yv[KN];
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
     const int64_t a = col0 + (int64_t)min(kb + kk, N) * COLS;
-    own[kk] = (AT)w[a];
-    yv[kk] = (AT)w[hy ? a + yoff : a];
+    c.own[kk] = w[a];
+    c.yv[kk] = hy ? w[a + yoff] : (TV)0;
   }
   const int64_t lo = col0 - dz + (int64_t)N * COLS, hi = col0 + dz;
-  const AT zl = (AT)w[z_lo ? lo : col0];
-  const AT zyl = (AT)w[z_lo && hy ? lo + yoff : col0];
-  const AT zh = (AT)w[z_hi ? hi : col0];
-  const AT zyh = (AT)w[z_hi && hy ? hi + yoff : col0];
-  const AT pl = hy ? zl + zyl : zl, ph = hy ? zh + zyh : zh;
+  c.zl = z_lo ? w[lo] : (TV)0;
+  c.zyl = z_lo && hy ? w[lo + yoff] : (TV)0;
+  c.zh = z_hi ? w[hi] : (TV)0;
+  c.zyh = z_hi && hy ? w[hi + yoff] : (TV)0;
+}
+
+// The A values (y and z pairs) of a loaded column, added in type AT.  A
+// missing copy adds an exact zero.  Callers issue every load of the tile
+// (upd_column_load) before the first call, so that all of them are in flight
+// together: one HBM round trip per tile.
+template <int N1, int KN, typename TV, typename AT = double>
+__device__ __forceinline__ void upd_column_sum(const ColumnW<KN, TV> &c, int kb, AT (&A)[KN]) {
+  constexpr int N = N1 - 1;
+  const AT pl = (AT)c.zl + (AT)c.zyl;
+  const AT ph = (AT)c.zh + (AT)c.zyh;
 #pragma unroll
   for (int kk = 0; kk < KN; ++kk) {
-    A[kk] = hy ? own[kk] + yv[kk] : own[kk];
-    if (z_lo && kb + kk == 0) A[kk] = A[kk] + pl;
-    if (z_hi && kb + kk == N) A[kk] = A[kk] + ph;
+    AT a = (AT)c.own[kk] + (AT)c.yv[kk];
+    if (kb + kk == 0) a = a + pl;
+    if (kb + kk == N) a = a + ph;
+    A[kk] = a;
   }
 }
+
+// Linear tile: the items of a thread are taken kLinGroup at a time, all
+// loads of a group (r, Minv and every present copy of w) before any sum, so
+// a group costs one HBM round trip.
+constexpr int kLinGroup = 4;
 
 template <int N1>
 __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
@@ -124,21 +147,38 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
                                                  const double *__restrict__ w,
                                                  const double *__restrict__ minv, double alpha,
                                                  double *sred, int tid) {
+  static_assert(kVecItems % kLinGroup == 0, "linear update groups must tile the items");
   const int64_t L = b.L();
   double rr = 0.0, rz = 0.0;
   const int64_t base = tile * kVecTile + tid;
 #pragma unroll
-  for (int u = 0; u < kVecItems; ++u) {
-    const int64_t idx = base + (int64_t)u * kVecThreads;
-    if (idx < L) {
+  for (int g = 0; g < kVecItems; g += kLinGroup) {
+    double rv[kLinGroup], mv[kLinGroup], v[kLinGroup][8], c[kLinGroup];
+    bool upd[kLinGroup];
+#pragma unroll
+    for (int u = 0; u < kLinGroup; ++u) {
+      const int64_t raw = base + (int64_t)(g + u) * kVecThreads;
+      const int64_t idx = raw < L ? raw : L - 1;
       const Node<N1> n = node_at<N1>(b, idx);
-      if (!n.boundary) {
-        const double wa = gather_copies<N1>(w, b, n, idx);
-        const double rt = ld_once(r + idx) - alpha * wa;
-        r[idx] = rt;
-        const double c = n.inv_mult();
-        rr += c * rt * rt;
-        rz += c * rt * (minv_at(minv, r, idx) * rt);
+      upd[u] = raw < L && !n.boundary;
+      c[u] = n.inv_mult();
+      rv[u] = ld_once(r + idx);
+      mv[u] = minv_at(minv, r, idx);
+      const Copies<N1> cp = copies_of<N1>(b, n, idx);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[u][q] = cp.valid[q] ? w[cp.addr[q]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLinGroup; ++u) {
+      if (upd[u]) {
+        // the copies in ascending element-local order (a missing one adds +0)
+        double wa = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wa += v[u][q];
+        const double rt = rv[u] - alpha * wa;
+        r[base + (int64_t)(g + u) * kVecThreads] = rt;
+        rr += c[u] * rt * rt;
+        rz += c[u] * rt * (mv[u] * rt);
       }
     }
   }
@@ -213,16 +253,22 @@ __device__ inline void column_copy_sums(const ColumnPos<N1, TV, V> &p, const TV 
                                         double *sA, AT (&S)[UpdTile<N1, TV, V>::KN]) {
   using U = UpdTile<N1, TV, V>;
   constexpr int N = U::N, COLS = U::COLS, NP = U::NP, KN = U::KN;
-  AT A[KN];
-  upd_column<N1, KN, TV, AT>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, A);
-  AT X[KN];
-#pragma unroll
-  for (int kk = 0; kk < KN; ++kk) X[kk] = (AT)0;
+  // every load first (own column, then the x copy column where it lies in
+  // another tile), so that both are in flight together; the branch holds
+  // loads only (zeros where the column has no x copy there)
+  ColumnW<KN, TV> cw, cx;
+  upd_column_load<N1, KN, TV>(w, p.col0, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, cw);
   if (p.hx && !p.x_in) {
-    // the x copy column lies in the neighbouring element of another tile
     const int64_t xc = p.i == 0 ? p.col0 - NP + N : p.col0 + NP - N;
-    upd_column<N1, KN, TV, AT>(w, xc, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, X);
+    upd_column_load<N1, KN, TV>(w, xc, p.kb, p.hy, p.yoff, p.z_lo, p.z_hi, p.dz, cx);
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KN; ++kk) cx.own[kk] = cx.yv[kk] = (TV)0;
+    cx.zl = cx.zyl = cx.zh = cx.zyh = (TV)0;
   }
+  AT A[KN], X[KN];
+  upd_column_sum<N1, KN, TV, AT>(cw, p.kb, A);
+  upd_column_sum<N1, KN, TV, AT>(cx, p.kb, X);
   if constexpr (U::EPT > 1) {
     // slot (element, thread's plane range, plane, column)
 #pragma unroll
