@@ -102,7 +102,8 @@ def _cg_traffic_frac(iters: int, wall: float):
         return None
     per_iter = 0.0
     for name, v in d.get("all_kernels", {}).items():
-        if "ax_mfma_kernel<8, semk::PrecF64, true>" in name or "cg_update_kernel<8, double>" in name:
+        # the CG operator and the default update tile (shape 0) of this order
+        if "ax_mfma_kernel<8, semk::PrecF64, true>" in name or "cg_update_kernel<8, double, 0>" in name:
             per_iter += v["hbm_bytes"]
     if per_iter == 0.0:
         return None
