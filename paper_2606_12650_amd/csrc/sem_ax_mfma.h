@@ -88,6 +88,23 @@ struct MfmaOps<PrecF64> {
   static constexpr bool kF64 = true;
 };
 
+// Where the FP64 tile loads G (ax_tile_mfma): with the operand, or from N = 8
+// after the gradient, which keeps the kernel's registers down.  The A.u alone
+// (no CG prologue) at N = 11 loads G with the operand and is held to eight
+// waves per SIMD (64 VGPRs, two 16-wave work-groups per CU; the compiler
+// spills three values): measured on MI355X, 32^3 box, 694 -> 649 us.  At
+// N = 8, 9, 10 and 12 the same change measured 6 % faster to 80 % slower
+// (296 -> 314, 388 -> 384, 525 -> 709, 644 -> 1159 us: spills), so those
+// orders keep the late loads.
+template <int N1, class P, bool CG>
+constexpr bool mfma_late_g() {
+  return MfmaOps<P>::kF64 && N1 >= 9 && (CG || N1 != 12);
+}
+template <int N1, class P, bool CG>
+constexpr int mfma_waves_per_simd() {
+  return (MfmaOps<P>::kF64 && N1 == 12 && !CG) ? 8 : 1;
+}
+
 // Result row of register v in lane group g.
 template <class P>
 __device__ __forceinline__ int mfma_row(int g, int v) {
@@ -260,12 +277,12 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
       rv[m] = ld_once(r + idx[m]);
     }
   }
-  // G with the prologue's loads, or in FP64 from N = 8 (LATE_G) after the
-  // gradient, so that the gradient's MFMA accumulators and G are never live
-  // together: at N = 11 the kernel then holds 70 instead of 98 VGPRs, three
-  // work-groups per CU instead of two (measured on MI355X: CG iteration
-  // 466 -> 408 us; at N = 7 and for FP32 / BF16 the early loads were faster).
-  constexpr bool LATE_G = MfmaOps<P>::kF64 && N1 >= 9;
+  // G with the prologue's loads, or in FP64 from N = 8 (LATE_G, mfma_late_g)
+  // after the gradient, so that the gradient's MFMA accumulators and G are
+  // never live together: the N = 11 CG operator then holds 70 instead of 98
+  // VGPRs (measured on MI355X: CG iteration 466 -> 408 us; at N = 7 and for
+  // FP32 / BF16 the early loads were faster).
+  constexpr bool LATE_G = mfma_late_g<N1, P, CG>();
   TC gk[PPT][6];
   auto load_gk = [&]() {
 #pragma unroll

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(OpCfg<N1>::THREADS, OpCfg<N1>::MIN_WAVES)
 // The operator with the D contractions on the matrix cores (sem_ax_mfma.h):
 // ceil((N+1)^2 / 16) waves per element.
 template <int N1, class P, bool CG>
-__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS)
+__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS, (mfma_waves_per_simd<N1, P, CG>()))
     ax_mfma_kernel(int64_t E, const typename P::TC *__restrict__ Dg,
                    const typename P::TG *__restrict__ G, typename P::TV *u,
                    typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,

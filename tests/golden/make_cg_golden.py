@@ -18,9 +18,9 @@ a thread pool and concatenates them (the first application is checked to be
 bitwise equal to the oracle's whole-mesh evaluation); the gather-scatter and
 mask are the oracle's.
 
-Usage (CPU only; the 32^3 N = 7 case takes about half an hour, N = 11 a few hours):
+Usage (CPU only; the 32^3 N = 7 case takes about 40 minutes, 16^3 at N = 11 about 20):
     python tests/golden/make_cg_golden.py --N 7
-    python tests/golden/make_cg_golden.py --N 11
+    python tests/golden/make_cg_golden.py --n 16 --N 11
 Outputs tests/golden/cg_box{n}_n{N}.json and tests/golden/cg_box{n}_n{N}_x.npz.
 """
 

@@ -11,11 +11,10 @@ Criteria (CG iterates are not unique in finite precision; any x that meets
 the residual is a correct solution):
   FP64 solve
   - iteration counts within 2 of the oracle's;
-  - both true relative residuals ||b - A x||_c / ||b||_c <= 1e-8 (1 + 1e-3).
-    The GPU's is computed with the oracle's operator on the N = 7 box; on the
-    N = 11 box the oracle's set-up of G alone takes minutes, so there it is
-    computed with the GPU's FP64 operator (which matches the oracle's to
-    1e-12 in the A.u parity tests);
+  - both true relative residuals ||b - A x||_c / ||b||_c <= 1e-8 (1 + 1e-3),
+    the GPU's computed with the oracle's operator (on a stored problem above
+    2e7 points, whose oracle set-up would take minutes, with the GPU's FP64
+    operator, which matches the oracle's to 1e-12 in the A.u parity tests);
   - the recursive residual ratios of the first 20 iterations within 1e-6
     (relative) of the oracle's;
   - x on the sampled elements within 1e-6 (c-weighted, relative) of the
