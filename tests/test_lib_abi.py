@@ -39,6 +39,12 @@ def test_workspace_bytes_host_only():
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
     bad = L.SemMeshDesc(1, 1, 1, 16, 0.0, 0, 0)  # above the run-time compiled orders 13..15
     assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
+    # the 32-bit index arithmetic caps a mesh at 4e9 element-local points
+    big = L.SemMeshDesc(193, 193, 193, 7, 0.0, 0, 0)  # 3.68e9 points
+    assert lib.sem_workspace_bytes(ctypes.byref(big)) > 80 * 193 ** 3 * 512
+    for n, N in ((200, 7), (100, 15), (256, 12)):  # 4.1e9, 4.1e9, 3.7e10 points
+        bad = L.SemMeshDesc(n, n, n, N, 0.0, 0, 0)
+        assert lib.sem_workspace_bytes(ctypes.byref(bad)) == 0
     # unknown flag bits are refused; the matrix-core flag costs no memory
     for flags in (3, 4, -1):
         bad = L.SemMeshDesc(2, 2, 2, 7, 0.0, L.SEM_F32, flags)
