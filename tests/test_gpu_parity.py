@@ -209,7 +209,7 @@ def test_cg_fixed_iterations_config1(mfma):
     N = 7
     pr = op.Problem(nx, ny, nz, N, 0.0)
     b = workload.continuous_rhs(2, nx, ny, nz, N)
-    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, fixed_iter=50)
+    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, fixed_iter=50, history=True)
     A = sem.SemOperator(nx, ny, nz, N, 0.0, device=DEV, mfma=mfma)
     xg, res = A.cg(_gpu(b), fixed_iter=50)
     assert res.iters == 50 and res.status == 0
@@ -217,6 +217,12 @@ def test_cg_fixed_iterations_config1(mfma):
     err = _c_norm(x - xr.reshape(-1), pr.c) / _c_norm(xr, pr.c)
     assert err <= 1e-9
     assert abs(res.rel_res - info["rel_res"]) <= 1e-6 * info["rel_res"]
+    # the recursive residual history of the first 20 iterations
+    xh = torch.empty_like(xg)
+    for k in range(1, 21):
+        _, rk = A.cg(_gpu(b), xh, fixed_iter=k)
+        ref = info["res_hist"][k - 1]
+        assert abs(rk.rel_res - ref) <= 1e-6 * ref, (k, rk.rel_res, ref)
     # a second solve gives the same bits (fixed reduction order), also when it
     # runs as a captured graph on a side stream
     x2, res2 = A.cg(_gpu(b), fixed_iter=50)
