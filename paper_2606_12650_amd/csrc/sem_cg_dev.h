@@ -141,19 +141,20 @@ __device__ __forceinline__ void upd_column_sum(const ColumnW<KN, TV> &c, int kb,
 // a group costs one HBM round trip.
 constexpr int kLinGroup = 4;
 
-template <int N1>
-__device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
-                                                 double *__restrict__ r,
-                                                 const double *__restrict__ w,
-                                                 const double *__restrict__ minv, double alpha,
+template <int N1, typename TV>
+__device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile, TV *__restrict__ r,
+                                                 const TV *__restrict__ w,
+                                                 const TV *__restrict__ minv, double alpha,
                                                  double *sred, int tid) {
   static_assert(kVecItems % kLinGroup == 0, "linear update groups must tile the items");
   const int64_t L = b.L();
+  const TV alpha_v = (TV)alpha;
   double rr = 0.0, rz = 0.0;
   const int64_t base = tile * kVecTile + tid;
 #pragma unroll
   for (int g = 0; g < kVecItems; g += kLinGroup) {
-    double rv[kLinGroup], mv[kLinGroup], v[kLinGroup][8], c[kLinGroup];
+    TV rv[kLinGroup], mv[kLinGroup], v[kLinGroup][8];
+    double c[kLinGroup];
     bool upd[kLinGroup];
 #pragma unroll
     for (int u = 0; u < kLinGroup; ++u) {
@@ -166,19 +167,21 @@ __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile,
       mv[u] = minv_at(minv, r, idx);
       const Copies<N1> cp = copies_of<N1>(b, n, idx);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[u][q] = cp.valid[q] ? w[cp.addr[q]] : 0.0;
+      for (int q = 0; q < 8; ++q) v[u][q] = cp.valid[q] ? w[cp.addr[q]] : (TV)0;
     }
 #pragma unroll
     for (int u = 0; u < kLinGroup; ++u) {
       if (upd[u]) {
-        // the copies in ascending element-local order (a missing one adds +0)
-        double wa = 0.0;
+        // the copies in ascending element-local order (a missing one adds +0),
+        // and r, in the vector type; the reductions in FP64
+        TV wa = (TV)0;
 #pragma unroll
         for (int q = 0; q < 8; ++q) wa += v[u][q];
-        const double rt = rv[u] - alpha * wa;
+        const TV rt = rv[u] - alpha_v * wa;
         r[base + (int64_t)(g + u) * kVecThreads] = rt;
-        rr += c[u] * rt * rt;
-        rz += c[u] * rt * (mv[u] * rt);
+        const double rd = (double)rt;
+        rr += c[u] * rd * rd;
+        rz += c[u] * rd * ((double)mv[u] * rd);
       }
     }
   }
@@ -292,7 +295,7 @@ __device__ inline TileSums cg_update_tile(const Box &b, int64_t tile, TV *__rest
                                           int tid) {
   using U = UpdTile<N1, TV, V>;
   if constexpr (U::LINEAR)
-    return cg_update_tile_linear<N1>(b, tile, r, w, minv, alpha, sred, tid);
+    return cg_update_tile_linear<N1, TV>(b, tile, r, w, minv, alpha, sred, tid);
   constexpr int N = U::N, COLS = U::COLS, KN = U::KN;
   const ColumnPos<N1, TV, V> p(b, tile, tid);
   // the copies of w are summed, and r updated, in the vector type (FP64, or

@@ -86,22 +86,18 @@ inline int64_t vec_grid_blocks(int64_t n) { return 8 * ((vec_num_blocks(n) + 7) 
 
 // Tiles of the CG update (the gather-scatter pulled into r -= alpha w) are
 // element-aligned: upd_ept consecutive elements with upd_ks threads per
-// (i, j) column, over all planes or, at the highest orders, over one of
-// upd_kp plane ranges.  Up to order 7 a tile fills 256 threads; above, it
-// holds two elements in FP64 (up to 512 threads) and one in FP32 (at order
-// 11 with two threads per column rather than two plane ranges).  The FP64
-// update from order 9 up keeps linear streaming tiles of kVecTile entries.
-// All of these choices are what measured faster on MI355X.
-__host__ __device__ constexpr int upd_ks(int n1, bool f64) {
-  return n1 == 9 ? 3 : ((n1 == 10 || n1 == 11 || (!f64 && n1 == 12)) ? 2 : 1);
-}
+// (i, j) column over all planes.  Up to order 7 a tile fills 256 threads; at
+// order 8 it holds two FP64 elements or one FP32 element with three threads
+// per column; at orders 9 and 10 the FP32 tile holds two elements with one
+// thread per column.  The FP64 update from order 9 and the FP32 update from
+// order 11 keep linear streaming tiles of kVecTile entries.  All of these
+// are the candidates (upd_shape) that measured fastest per CG iteration on
+// MI355X.
+__host__ __device__ constexpr int upd_ks(int n1, bool f64) { return n1 == 9 ? 3 : 1; }
 __host__ __device__ constexpr int upd_ept(int n1, bool f64) {
-  return n1 >= 9 ? (f64 ? 2 : 1) : kVecThreads / (upd_ks(n1, f64) * n1 * n1);
+  return n1 == 9 ? (f64 ? 2 : 1) : n1 >= 10 ? 2 : kVecThreads / (n1 * n1);
 }
-__host__ __device__ constexpr int upd_kp(int n1, bool f64) {
-  return (n1 >= 13 || (f64 && n1 == 12)) ? 2 : 1;
-}
-__host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return f64 && n1 >= 10; }
+__host__ __device__ constexpr bool upd_linear(int n1, bool f64) { return n1 >= (f64 ? 10 : 12); }
 
 // Candidate update tiles for tuning: shape v of an order and vector type
 // (threads per column, elements per tile, plane ranges per element).  v = 0
@@ -117,7 +113,7 @@ struct UpdShape {
 constexpr int kUpdVariants = 4;
 __host__ __device__ constexpr UpdShape upd_shape(int n1, bool f64, int v) {
   if (v == 0)
-    return upd_linear(n1, f64) ? UpdShape{0, 0, 0} : UpdShape{upd_ks(n1, f64), upd_ept(n1, f64), upd_kp(n1, f64)};
+    return upd_linear(n1, f64) ? UpdShape{0, 0, 0} : UpdShape{upd_ks(n1, f64), upd_ept(n1, f64), 1};
   if (v < 0 || v >= kUpdVariants) return UpdShape{-1, 0, 0};
   switch (n1) {
     case 2: return v == 1 ? UpdShape{1, 128, 1} : v == 2 ? UpdShape{1, 32, 1} : UpdShape{2, 32, 1};
@@ -132,16 +128,16 @@ __host__ __device__ constexpr UpdShape upd_shape(int n1, bool f64, int v) {
       return v == 1 ? UpdShape{1, 4, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{3, 2, 1};
     case 10:
       if (f64) return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{1, 4, 1};
-      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{1, 4, 1};
+      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{1, 4, 1};
     case 11:
       if (f64) return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{1, 2, 1};
-      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{4, 1, 1};
+      return v == 1 ? UpdShape{2, 2, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{4, 1, 1};
     case 12:
       if (f64) return v == 1 ? UpdShape{1, 2, 2} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{3, 1, 1};
-      return v == 1 ? UpdShape{3, 1, 1} : v == 2 ? UpdShape{1, 2, 1} : UpdShape{2, 1, 2};
+      return v == 1 ? UpdShape{3, 1, 1} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{2, 1, 2};
     case 13:
       if (f64) return v == 1 ? UpdShape{1, 2, 2} : v == 2 ? UpdShape{2, 1, 1} : UpdShape{3, 1, 1};
-      return v == 1 ? UpdShape{2, 1, 1} : v == 2 ? UpdShape{3, 1, 1} : UpdShape{2, 1, 2};
+      return v == 1 ? UpdShape{2, 1, 1} : v == 2 ? UpdShape{3, 1, 1} : UpdShape{1, 1, 2};
     default: return UpdShape{-1, 0, 0};
   }
 }
