@@ -32,23 +32,32 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published peak
 METRIC = "GDOF/s A·u and CG solves/s, mixed vs FP64 at 1e-8 rel res; p99 latency"
 
 
-def _kernel_source_hash() -> str:
+def _source_digest(files) -> str:
+    """Hash of the kernel sources' code: comments and blank lines are left out,
+    so that a comment edit keeps committed counter runs valid."""
+    import re
+
     h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h",
-              "sem_kernels.h", "sem_types.h"):
-        with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode("utf-8"))
     return h.hexdigest()[:16]
+
+
+def _kernel_source_hash() -> str:
+    return _source_digest(("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h",
+                           "sem_device.h", "sem_kernels.h", "sem_types.h"))
 
 
 def _cg_source_hash() -> str:
     """Hash of every source the CG iteration's kernels are built from."""
-    h = hashlib.sha256()
-    for f in ("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h", "sem_device.h",
-              "sem_kernels.h", "sem_types.h", "sem_cg_dev.h", "sem_vec.hip"):
-        with open(os.path.join(ROOT, "paper_2606_12650_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    return _source_digest(("sem_ax.hip", "sem_ax_mfma.h", "sem_ax_tile.h", "sem_internal.h",
+                           "sem_device.h", "sem_kernels.h", "sem_types.h", "sem_cg_dev.h",
+                           "sem_vec.hip"))
 
 
 def _traffic_from_profile(kernel_hash: str):

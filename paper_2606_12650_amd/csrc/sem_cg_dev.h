@@ -66,8 +66,9 @@ __device__ inline TileSums cg_init_tile(const Box &b, int64_t L, int64_t tile,
 // that column is in the tile and is recomputed from w otherwise.  A missing
 // copy is not loaded and adds an exact zero.
 // The work-group has BLOCK threads; tid is threadIdx.x.  LINEAR tiles (FP64
-// from order 9) take kVecTile consecutive entries instead, each node summing
-// its copies in ascending element-local order with missing copies masked.
+// from order 9, FP32 from order 11) take kVecTile consecutive entries
+// instead, each node summing its copies in ascending element-local order with
+// missing copies masked.
 // V selects one of the candidate shapes of upd_shape (0: the default).
 template <int N1, typename TV, int V = 0>
 struct UpdTile {
