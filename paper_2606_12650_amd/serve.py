@@ -118,6 +118,9 @@ class Scheduler:
     side) runs while the batched step of the admitted requests is on the
     GPU, and only the cheap insertion of prepared requests into the batch
     happens between steps.  A prepared request holds its slot and memory.
+    With ``step_done() -> bool`` as well, set-ups stop once the running step
+    has ended (after at least one), so a burst of arrivals does not leave
+    the device idle while the host prepares it.
     """
 
     def __init__(self, executor, hbm_budget: int, max_slots: int, clock=None, sleep=None):
@@ -188,9 +191,17 @@ class Scheduler:
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
 
-        def prepare_queued():
+        step_done = getattr(self.ex, "step_done", None)
+
+        def prepare_queued(boxed: bool):
+            # boxed: stop once the device is free (the running step has
+            # ended, or none runs) so that the next step does not wait for
+            # set-ups; one set-up always goes ahead, so admission keeps moving
             nonlocal used
+            n = 0
             while queue and len(active) + len(prepared) < self.max_slots:
+                if boxed and n > 0 and step_done is not None and step_done():
+                    break
                 req = queue[0]
                 fp = self.ex.footprint(req)
                 if fp > self.budget:  # can never fit: refuse rather than block the queue
@@ -202,13 +213,14 @@ class Scheduler:
                 queue.popleft()
                 adm = self.clock() - start
                 prepared.append((req, self.ex.prepare(req), fp, adm))
+                n += 1
                 used += fp
                 stats.peak_bytes = max(stats.peak_bytes, used)
 
         while pending or queue or prepared or active:
             take_arrivals()
             if not active and not prepared:
-                prepare_queued()  # nothing on the device: prepare now
+                prepare_queued(boxed=True)  # nothing on the device: start it soon
             while prepared:
                 req, token, fp, adm = prepared.popleft()
                 active[self.ex.admit_prepared(token)] = (req, fp, adm)
@@ -217,7 +229,7 @@ class Scheduler:
                 self.ex.launch_step()
                 # the step runs on the device: admit what has arrived meanwhile
                 take_arrivals()
-                prepare_queued()
+                prepare_queued(boxed=True)
                 done = self.ex.poll()
                 tnow = self.clock() - start
                 for slot, res in done:
@@ -309,6 +321,10 @@ class GpuExecutor:
 
     def step(self) -> None:
         self.launch_step()
+
+    def step_done(self) -> bool:
+        """The launched step has finished on the device (no wait)."""
+        return self._events is None or self._events[1].query()
 
     def poll(self):
         fin, _ = self.batch.poll()  # waits for the step
