@@ -106,7 +106,10 @@ def test_many_slots_and_tile_change_between_steps():
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_mixed_batched_matches_alone(prec):
-    cases = [((3, 3, 2), 5), ((2, 3, 3), 7), ((2, 2, 3), 3), ((2, 2, 2), 9)]
+    # every inner update tile family: column tiles (N = 3, 5, 7), two elements
+    # per tile (N = 9, 10) and the linear tile (N = 11)
+    cases = [((3, 3, 2), 5), ((2, 3, 3), 7), ((2, 2, 3), 3), ((2, 2, 2), 9), ((1, 2, 3), 10),
+             ((2, 2, 1), 11)]
     insts = [_instance(20 + i, *m, N, lowprec=prec) for i, (m, N) in enumerate(cases)]
     alone = []
     for A, b in insts:
