@@ -88,7 +88,7 @@ def test_update_tile_variants_fp64_match_oracle(N):
     A.close()
 
 
-@pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 11, 12])
+@pytest.mark.parametrize("N", [1, 3, 5, 7, 9, 10, 11, 12])
 @pytest.mark.parametrize("lowprec", ["f32", "bf16"])
 def test_inner_update_tile_variants_mixed_solve(N, lowprec):
     nx, ny, nz = _mesh(N)
