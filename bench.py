@@ -268,7 +268,8 @@ AX_BYTES_PER_POINT = {"f64": 64.0, "f32": 32.0, "bf16": 20.0}
 
 def _ax_kernel_name(prec: str, N: int, mfma: bool) -> str:
     P = {"f64": "PrecF64", "f32": "PrecF32", "bf16": "PrecBF16"}[prec]
-    return f"{'ax_mfma_kernel' if mfma else 'ax_kernel'}<{N + 1}, {P}, false>"
+    # the element-local sem_ax runs the matrix-core tile's streaming-store kernel
+    return f"ax_mfma_local_kernel<{N + 1}, {P}>" if mfma else f"ax_kernel<{N + 1}, {P}, false>"
 
 
 def _default_is_mfma(prec: str, N: int) -> bool:
@@ -319,7 +320,7 @@ def bench_ax_study(args, dev, orders=(7, 11)) -> dict:
                     if mf:
                         P = {"f64": "PrecF64", "f32": "PrecF32", "bf16": "PrecBF16"}[prec]
                         row[key]["mfma"] = _mfma_from_profile(_kernel_source_hash(),
-                                                              f"ax_mfma_kernel<{N + 1}, semk::{P}, false>")
+                                                              f"ax_mfma_local_kernel<{N + 1}, semk::{P}>")
                     print(f"[bench] ax N={N} {key}: {row[key]}", file=sys.stderr, flush=True)
                     A.close()
                     del A, w
@@ -1036,7 +1037,7 @@ def main(argv=None) -> int:
         "ax_masked_gdofs": gdof / axm_s / 1e9,
         "gs_csr": gs_info,
         "roofline": {
-            "kernel": "ax_mfma_kernel<8, PrecF64, false> (sem_ax element operator, N=7: the "
+            "kernel": "ax_mfma_local_kernel<8, PrecF64> (sem_ax element operator, N=7: the "
                       "matrix-core tile, the library default at this order)",
             "bound": "hbm",
             "achieved": achieved,
@@ -1051,7 +1052,7 @@ def main(argv=None) -> int:
             "kernel_source_hash": khash,
             # the D contractions on the matrix cores (f64 MFMA), from the
             # committed counter run: not the bound, reported beside it
-            "mfma": _mfma_from_profile(khash, "ax_mfma_kernel<8, semk::PrecF64, false>"),
+            "mfma": _mfma_from_profile(khash, "ax_mfma_local_kernel<8, semk::PrecF64>"),
         },
     }
     if ax_study is not None:

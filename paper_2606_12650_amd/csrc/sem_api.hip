@@ -474,9 +474,9 @@ int sem_ax(sem_ctx *ctx, const double *u, double *w, int mode, void *stream) {
   if (mode != SEM_AX_LOCAL && mode != SEM_AX_ASSEMBLED && mode != SEM_AX_MASKED)
     return fail(SEM_ERR_ARG, "sem_ax: mode must be SEM_AX_LOCAL, SEM_AX_ASSEMBLED or SEM_AX_MASKED");
   hipStream_t s = (hipStream_t)stream;
-  if (mode == SEM_AX_LOCAL) {
+  if (mode == SEM_AX_LOCAL) {  // the result goes to the caller: streamed stores
     SEM_HIP(semk::launch_ax_f64(ctx->box, ctx->op_impl[0], ctx->D, ctx->G, const_cast<double *>(u), w, nullptr,
-                                nullptr, nullptr, nullptr, nullptr, s));
+                                nullptr, nullptr, nullptr, nullptr, s, true));
     return SEM_OK;
   }
   // element-local result into the workspace, then the gather-scatter pull
@@ -581,7 +581,7 @@ int sem_ax_lowp(sem_ctx *ctx, const float *u, float *w, int mode, void *stream) 
   float *dst = mode == SEM_AX_LOCAL ? w : ctx->win;
   SEM_HIP(semk::launch_ax_lowp(ctx->box, ctx->desc.lowprec, ctx->op_impl[1], ctx->Dlo,
                                ctx->Glo, const_cast<float *>(u), dst, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, s));
+                               nullptr, s, mode == SEM_AX_LOCAL));
   if (mode != SEM_AX_LOCAL)
     SEM_HIP(semk::launch_gather_f32(ctx->box, ctx->win, w,
                                     mode == SEM_AX_MASKED ? semk::kGatherMasked : semk::kGatherAssembled, s));

@@ -50,7 +50,8 @@ hipError_t ax_dispatch(const Box &b, const void *D, const void *G, void *u, void
 
 template <int N1, class P>
 hipError_t mfma_dispatch(const Box &b, const void *D, const void *G, void *u, void *w, const void *r,
-                         const void *minv, void *x, CgState *cg, double *part, hipStream_t s) {
+                         const void *minv, void *x, CgState *cg, double *part, hipStream_t s,
+                         bool stream_w) {
   using C = MfmaCfg<N1>;
   using TV = typename P::TV;
   using TG = typename P::TG;
@@ -61,6 +62,9 @@ hipError_t mfma_dispatch(const Box &b, const void *D, const void *G, void *u, vo
     hipLaunchKernelGGL((ax_mfma_kernel<N1, P, true>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                        b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
                        (const TV *)minv, (TV *)x, cg, part);
+  else if (stream_w)
+    hipLaunchKernelGGL((ax_mfma_local_kernel<N1, P>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w);
   else
     hipLaunchKernelGGL((ax_mfma_kernel<N1, P, false>), dim3((unsigned)blocks), dim3(C::THREADS), 0,
                        s, b.E(), (const TC *)D, (const TG *)G, (TV *)u, (TV *)w, (const TV *)r,
@@ -106,12 +110,12 @@ int64_t ax_num_blocks(const Box &b) {
 template <class P>
 hipError_t ax_launch(const Box &b, int cls, int impl, const void *D, const void *G, void *u, void *w,
                      const void *r, const void *minv, void *x, CgState *cg, double *part,
-                     hipStream_t s) {
+                     hipStream_t s, bool stream_w) {
   const bool mfma = impl == kImplMfma || (impl == kImplDefault && op_uses_mfma(cls, b.N));
   switch (b.N) {
 #define CASE(n)                                                                      \
   case n:                                                                            \
-    return mfma ? mfma_dispatch<n + 1, P>(b, D, G, u, w, r, minv, x, cg, part, s)   \
+    return mfma ? mfma_dispatch<n + 1, P>(b, D, G, u, w, r, minv, x, cg, part, s, stream_w) \
                 : ax_dispatch<n + 1, P>(b, D, G, u, w, r, minv, x, cg, part, s);
     SEM_FOR_EACH_ORDER(CASE)
 #undef CASE
@@ -122,17 +126,19 @@ hipError_t ax_launch(const Box &b, int cls, int impl, const void *D, const void 
 
 hipError_t launch_ax_f64(const Box &b, int impl, const double *D, const double *G, double *u,
                          double *w, const double *r, const double *minv, double *x, CgState *cg,
-                         double *part, hipStream_t s) {
+                         double *part, hipStream_t s, bool stream_w) {
   if (rtc_order(b.N))  // run-time kernels: the matrix-core tile only
     return impl == kImplValu ? hipErrorInvalidValue : rtc_ax_f64(b, D, G, u, w, r, minv, x, cg, part, s);
-  return ax_launch<PrecF64>(b, 0, impl, D, G, u, w, r, minv, x, cg, part, s);
+  return ax_launch<PrecF64>(b, 0, impl, D, G, u, w, r, minv, x, cg, part, s, stream_w);
 }
 
 hipError_t launch_ax_lowp(const Box &b, int prec, int impl, const float *D, const void *G, float *u,
                           float *w, const float *r, const float *minv, float *x, CgState *cg,
-                          double *part, hipStream_t s) {
-  if (prec == SEM_F32) return ax_launch<PrecF32>(b, 1, impl, D, G, u, w, r, minv, x, cg, part, s);
-  if (prec == SEM_BF16) return ax_launch<PrecBF16>(b, 2, impl, D, G, u, w, r, minv, x, cg, part, s);
+                          double *part, hipStream_t s, bool stream_w) {
+  if (prec == SEM_F32)
+    return ax_launch<PrecF32>(b, 1, impl, D, G, u, w, r, minv, x, cg, part, s, stream_w);
+  if (prec == SEM_BF16)
+    return ax_launch<PrecBF16>(b, 2, impl, D, G, u, w, r, minv, x, cg, part, s, stream_w);
   return hipErrorInvalidValue;
 }
 

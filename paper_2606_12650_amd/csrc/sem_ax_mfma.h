@@ -210,13 +210,14 @@ __device__ __forceinline__ void mfma_store(typename P::TC *out, const typename M
 
 // Same contract as ax_tile<N1, EPB, P, CG, OPQ> with blockDim = MfmaCfg<N1>::THREADS
 // (EPB = MfmaCfg<N1>::EPB).  LDS: sD N1*N1 TC, s1/s2/s3 EPB * AxTile<N1>::TILE
-// TC each, sred blockDim / 64 doubles.
+// TC each, sred blockDim / 64 doubles.  SW (without CG): w is written with
+// non-temporal stores.
 //
 // HBM traffic runs in the flat layout: the element's 64 NT threads take its
 // nodes in index order (thread t: nodes t, t + 64 NT, ...), so every load and
 // store is a run of 64 consecutive values.  The t-direction results pass
 // through LDS to meet that layout.
-template <int N1, int EPB, class P, bool CG, bool OPQ = false>
+template <int N1, int EPB, class P, bool CG, bool OPQ = false, bool SW = false>
 __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typename P::TC *__restrict__ Dg,
                                              const typename P::TG *__restrict__ G, typename P::TV *u,
                                              typename P::TV *__restrict__ w,
@@ -362,7 +363,14 @@ __device__ __forceinline__ void ax_tile_mfma(int64_t E, int64_t e0, const typena
       if (lt + NTT * m < NP) {
         const int o = off[m];
         const TC val = (R[o] + S[o]) + U[o];
-        if (okv[m]) w[idx[m]] = (TV)val;
+        if (okv[m]) {
+          // a result the caller takes as it is (SEM_AX_LOCAL) is streamed
+          // past the caches; one a gather reads next is kept there
+          if constexpr (!CG && SW)
+            st_once(w + idx[m], (TV)val);
+          else
+            w[idx[m]] = (TV)val;
+        }
         acc += (double)uk[m] * (double)val;
       }
     }

@@ -40,10 +40,12 @@ hipError_t launch_fill_c(const Box &b, double *c, hipStream_t s);
 // w = A_L u.  With cg != null (a CG iteration) a prologue first finishes the
 // previous iteration, x += alpha p, then forms p <- Minv r + beta p (u is p,
 // updated in place), and the per-element sums of p.w go to part (E of them).
-// impl: an OpImpl.
+// impl: an OpImpl.  stream_w: w goes to the caller as it is (no gather reads
+// it next), so the matrix-core tile writes it with non-temporal stores (the
+// orders compiled at run time keep plain stores).
 hipError_t launch_ax_f64(const Box &b, int impl, const double *D, const double *G, double *u,
                          double *w, const double *r, const double *minv, double *x, CgState *cg,
-                         double *part, hipStream_t s);
+                         double *part, hipStream_t s, bool stream_w = false);
 
 // Low-precision operator (prec SEM_F32 or SEM_BF16): FP32 vectors, G stored
 // as float or bfloat16 bits, D as float (bfloat16-rounded in BF16 mode),
@@ -51,7 +53,7 @@ hipError_t launch_ax_f64(const Box &b, int impl, const double *D, const double *
 // correction e).  impl: an OpImpl.
 hipError_t launch_ax_lowp(const Box &b, int prec, int impl, const float *D, const void *G, float *u,
                           float *w, const float *r, const float *minv, float *x, CgState *cg,
-                          double *part, hipStream_t s);
+                          double *part, hipStream_t s, bool stream_w = false);
 // dst[i] = src[i] rounded to float (SEM_F32) or to bfloat16 bits (SEM_BF16).
 hipError_t launch_convert_g(int prec, int64_t n, const double *src, void *dst, hipStream_t s);
 

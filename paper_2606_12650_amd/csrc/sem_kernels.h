@@ -64,13 +64,14 @@ __global__ void __launch_bounds__(OpCfg<N1>::THREADS, OpCfg<N1>::MIN_WAVES)
 
 // The operator with the D contractions on the matrix cores (sem_ax_mfma.h):
 // ceil((N+1)^2 / 16) waves per element.
-template <int N1, class P, bool CG>
-__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS, (mfma_waves_per_simd<N1, P, CG>()))
-    ax_mfma_kernel(int64_t E, const typename P::TC *__restrict__ Dg,
-                   const typename P::TG *__restrict__ G, typename P::TV *u,
-                   typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,
-                   const typename P::TV *__restrict__ minv, typename P::TV *__restrict__ x,
-                   CgState *__restrict__ st, double *__restrict__ part) {
+template <int N1, class P, bool CG, bool SW>
+__device__ __forceinline__ void ax_mfma_body(int64_t E, const typename P::TC *__restrict__ Dg,
+                                             const typename P::TG *__restrict__ G,
+                                             typename P::TV *u, typename P::TV *__restrict__ w,
+                                             const typename P::TV *__restrict__ r,
+                                             const typename P::TV *__restrict__ minv,
+                                             typename P::TV *__restrict__ x,
+                                             CgState *__restrict__ st, double *__restrict__ part) {
   using C = MfmaCfg<N1>;
   using TC = typename P::TC;
   __shared__ TC sD[N1 * N1];
@@ -84,8 +85,29 @@ __global__ void __launch_bounds__(MfmaCfg<N1>::THREADS, (mfma_waves_per_simd<N1,
     alpha = st->alpha;
     beta = st->beta;
   }
-  ax_tile_mfma<N1, C::EPB, P, CG>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv, x, alpha,
-                                  beta, part, sD, s1, s2, s3, sred);
+  ax_tile_mfma<N1, C::EPB, P, CG, false, SW>(E, (int64_t)blockIdx.x * C::EPB, Dg, G, u, w, r, minv,
+                                             x, alpha, beta, part, sD, s1, s2, s3, sred);
+}
+
+template <int N1, class P, bool CG>
+__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS, (mfma_waves_per_simd<N1, P, CG>()))
+    ax_mfma_kernel(int64_t E, const typename P::TC *__restrict__ Dg,
+                   const typename P::TG *__restrict__ G, typename P::TV *u,
+                   typename P::TV *__restrict__ w, const typename P::TV *__restrict__ r,
+                   const typename P::TV *__restrict__ minv, typename P::TV *__restrict__ x,
+                   CgState *__restrict__ st, double *__restrict__ part) {
+  ax_mfma_body<N1, P, CG, false>(E, Dg, G, u, w, r, minv, x, st, part);
+}
+
+// The element-local sem_ax, whose result goes to the caller as it is (no
+// gather reads it next): the same kernel with w written by non-temporal
+// stores.
+template <int N1, class P>
+__global__ void __launch_bounds__(MfmaCfg<N1>::THREADS, (mfma_waves_per_simd<N1, P, false>()))
+    ax_mfma_local_kernel(int64_t E, const typename P::TC *__restrict__ Dg,
+                         const typename P::TG *__restrict__ G, typename P::TV *u,
+                         typename P::TV *__restrict__ w) {
+  ax_mfma_body<N1, P, false, true>(E, Dg, G, u, w, nullptr, nullptr, nullptr, nullptr, nullptr);
 }
 
 // Metric setup: coordinates of the (deformed) box mesh, isoparametric
