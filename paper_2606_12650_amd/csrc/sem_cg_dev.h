@@ -142,50 +142,145 @@ __device__ __forceinline__ void upd_column_sum(const ColumnW<KN, TV> &c, int kb,
 // a group costs one HBM round trip.
 constexpr int kLinGroup = 4;
 
+// Neighbour bits of element (ex, ey, ez): bit 0 / 1 a neighbour below /
+// above in x, bits 2 / 3 in y, bits 4 / 5 in z.
+__host__ __device__ __forceinline__ uint32_t elem_nb_bits(const Box &b, uint32_t ex, uint32_t ey,
+                                                          uint32_t ez) {
+  return (ex > 0 ? 1u : 0u) | (ex + 1 < (uint32_t)b.nx ? 2u : 0u) | (ey > 0 ? 4u : 0u) |
+         (ey + 1 < (uint32_t)b.ny ? 8u : 0u) | (ez > 0 ? 16u : 0u) |
+         (ez + 1 < (uint32_t)b.nz ? 32u : 0u);
+}
+
+// Where the items of a thread of the linear tile sit.  The index arithmetic
+// is 32-bit (L < 2^32) and done once per thread where it can be: a thread's
+// items lie kVecThreads apart, so they span its first element and at most
+// the two after it, whose neighbour bits are found up front.  A node's face
+// bits (bit 0 / 1: i = 0 / N, 2 / 3: j, 4 / 5: k) against its element's
+// neighbour bits give everything else: a face bit with no neighbour is the
+// box boundary, one with a neighbour a shared copy (mult = 2^(shared
+// faces)), and copy q of the node sits a fixed, uniform step (off[q]) from
+// its lowest copy lo.
+template <int N1>
+struct LinItems {
+  static constexpr int N = N1 - 1;
+  static constexpr uint32_t NP = (uint32_t)N1 * N1 * N1;
+  static constexpr uint32_t dx = NP - N;  // to the same face node of the next element in x
+  static_assert(kVecThreads * (kVecItems - 1) < 2 * NP, "a thread's items span at most three elements");
+  uint32_t L, raw0, loc0, dy, dz;
+  uint32_t nbs;  // neighbour bits of the first element and the two after it, 6 bits each
+  struct Item {
+    uint32_t raw;  // the item's index (may lie past L)
+    uint32_t idx;  // raw, clamped into [0, L)
+    uint32_t sh;   // faces shared with a neighbour (0 past L)
+    uint32_t lo;   // the lowest copy of the node
+    bool live;     // raw < L
+    bool upd;      // live and not on the box boundary
+  };
+  __host__ __device__ LinItems(const Box &b, int64_t tile, int tid) {
+    L = (uint32_t)b.L();
+    dy = (uint32_t)b.nx * NP - (uint32_t)(N * N1);
+    dz = (uint32_t)b.nx * (uint32_t)b.ny * NP - (uint32_t)(N * N1 * N1);
+    raw0 = (uint32_t)(tile * kVecTile) + (uint32_t)tid;
+    const uint32_t e0 = raw0 / NP;
+    loc0 = raw0 - e0 * NP;
+    const uint32_t eyz = b.fdx.div(e0);
+    uint32_t ex = e0 - eyz * (uint32_t)b.nx;
+    const uint32_t ezz = b.fdy.div(eyz);
+    uint32_t ey = eyz - ezz * (uint32_t)b.ny, ez = ezz;
+    nbs = elem_nb_bits(b, ex, ey, ez);
+    next_element(b, ex, ey, ez);
+    nbs |= elem_nb_bits(b, ex, ey, ez) << 6;
+    next_element(b, ex, ey, ez);
+    nbs |= elem_nb_bits(b, ex, ey, ez) << 12;
+  }
+  __host__ __device__ static void next_element(const Box &b, uint32_t &ex, uint32_t &ey, uint32_t &ez) {
+    const bool wx = ex + 1 == (uint32_t)b.nx;
+    ex = wx ? 0u : ex + 1;
+    const bool wy = wx && ey + 1 == (uint32_t)b.ny;
+    ey = wy ? 0u : ey + (wx ? 1u : 0u);
+    ez += wy ? 1u : 0u;
+  }
+  __host__ __device__ uint32_t off(int q) const {
+    return ((q & 1) ? dx : 0u) + ((q & 2) ? dy : 0u) + ((q & 4) ? dz : 0u);
+  }
+  __host__ __device__ Item item(int u) const {
+    Item t;
+    t.raw = raw0 + (uint32_t)(u * kVecThreads);
+    t.live = t.raw < L;
+    t.idx = t.live ? t.raw : L - 1;
+    uint32_t loc = loc0 + (uint32_t)(u * kVecThreads);
+    const uint32_t steps = (loc >= NP ? 1u : 0u) + (loc >= 2 * NP ? 1u : 0u);
+    loc -= steps * NP;
+    const uint32_t enb = (nbs >> (6u * steps)) & 63u;
+    const uint32_t i = loc % N1, j = (loc / N1) % N1, k = loc / (N1 * N1);
+    const uint32_t fb = (i == 0 ? 1u : 0u) | (i == (uint32_t)N ? 2u : 0u) | (j == 0 ? 4u : 0u) |
+                        (j == (uint32_t)N ? 8u : 0u) | (k == 0 ? 16u : 0u) |
+                        (k == (uint32_t)N ? 32u : 0u);
+    t.sh = t.live ? (fb & enb) : 0u;
+    t.upd = t.live && (fb & ~enb) == 0u;
+    t.lo = t.idx - ((t.sh & 1u) ? dx : 0u) - ((t.sh & 4u) ? dy : 0u) - ((t.sh & 16u) ? dz : 0u);
+    return t;
+  }
+  // copy q of the node exists
+  __host__ __device__ static bool has_copy(uint32_t sh, int q) {
+    return (!(q & 1) || (sh & 3u)) && (!(q & 2) || (sh & 12u)) && (!(q & 4) || (sh & 48u));
+  }
+};
+
 template <int N1, typename TV>
 __device__ inline TileSums cg_update_tile_linear(const Box &b, int64_t tile, TV *__restrict__ r,
                                                  const TV *__restrict__ w,
                                                  const TV *__restrict__ minv, double alpha,
                                                  double *sred, int tid) {
   static_assert(kVecItems % kLinGroup == 0, "linear update groups must tile the items");
-  const int64_t L = b.L();
+  const LinItems<N1> P(b, tile, tid);
   const TV alpha_v = (TV)alpha;
   double rr = 0.0, rz = 0.0;
-  const int64_t base = tile * kVecTile + tid;
+  // the new r of every item is stored at the end: a store issued between
+  // two groups held the next group's loads back until it had completed
+  TV rnew[kVecItems];
+  bool upd[kVecItems];
 #pragma unroll
   for (int g = 0; g < kVecItems; g += kLinGroup) {
     TV rv[kLinGroup], mv[kLinGroup], v[kLinGroup][8];
     double c[kLinGroup];
-    bool upd[kLinGroup];
 #pragma unroll
     for (int u = 0; u < kLinGroup; ++u) {
-      const int64_t raw = base + (int64_t)(g + u) * kVecThreads;
-      const int64_t idx = raw < L ? raw : L - 1;
-      const Node<N1> n = node_at<N1>(b, idx);
-      upd[u] = raw < L && !n.boundary;
-      c[u] = n.inv_mult();
-      rv[u] = ld_once(r + idx);
-      mv[u] = minv_at(minv, r, idx);
-      const Copies<N1> cp = copies_of<N1>(b, n, idx);
+      const typename LinItems<N1>::Item t = P.item(g + u);
+      upd[g + u] = t.upd;
+      // 1 / mult: the exponent of 2^-(shared faces) set directly
+      c[u] = __hiloint2double((int)((1023u - (uint32_t)__builtin_popcount(t.sh)) << 20), 0);
+      rv[u] = ld_once(r + t.idx);
+      mv[u] = minv_at(minv, r, (int64_t)t.idx);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[u][q] = cp.valid[q] ? w[cp.addr[q]] : (TV)0;
+      for (int q = 0; q < 8; ++q)
+        v[u][q] = LinItems<N1>::has_copy(t.sh, q) ? w[t.lo + P.off(q)] : (TV)0;
     }
 #pragma unroll
     for (int u = 0; u < kLinGroup; ++u) {
-      if (upd[u]) {
-        // the copies in ascending element-local order (a missing one adds +0),
-        // and r, in the vector type; the reductions in FP64
-        TV wa = (TV)0;
+      // the copies in ascending element-local order (a missing one adds +0),
+      // and r, in the vector type; the reductions in FP64
+      TV wa = (TV)0;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) wa += v[u][q];
-        const TV rt = rv[u] - alpha_v * wa;
-        r[base + (int64_t)(g + u) * kVecThreads] = rt;
+      for (int q = 0; q < 8; ++q) wa += v[u][q];
+      const TV rt = rv[u] - alpha_v * wa;
+      rnew[g + u] = rt;
+      if (upd[g + u]) {
         const double rd = (double)rt;
         rr += c[u] * rd * rd;
         rz += c[u] * rd * ((double)mv[u] * rd);
       }
     }
+    // the next group's loads stay after this group's sums (all groups'
+    // loads at once would need registers for every copy of every item):
+    // an empty asm that takes the sums and orders memory accesses
+#pragma unroll
+    for (int u = 0; u < kLinGroup; ++u) asm volatile("" : "+v"(rnew[g + u]) : : "memory");
+    asm volatile("" : "+v"(rr), "+v"(rz) : : "memory");
   }
+#pragma unroll
+  for (int u = 0; u < kVecItems; ++u)
+    if (upd[u]) r[P.raw0 + (uint32_t)(u * kVecThreads)] = rnew[u];
   TileSums t;
   block_sum2<kVecThreads>(rr, rz, sred, &t.a, &t.b);
   return t;
