@@ -279,6 +279,25 @@ def test_cg_all_orders_ragged(N):
     assert _same_on_copies(pr, x)
 
 
+@pytest.mark.parametrize("mesh,N", [((1, 3, 2), 9), ((2, 1, 3), 10), ((3, 2, 1), 11), ((1, 1, 1), 11),
+                                    ((1, 1, 4), 9), ((4, 1, 1), 10)])
+def test_cg_linear_update_slab_meshes(mesh, N):
+    """20 FP64 PCG iterations at orders whose update runs the linear tile, on
+    meshes one element across in some direction and on a single element: a
+    thread's items there step over element rows, columns and layers at once."""
+    pr = op.Problem(*mesh, N, 0.05)
+    b = workload.continuous_rhs(90 + N, *mesh, N)
+    xr, info = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, fixed_iter=20)
+    A = sem.SemOperator(*mesh, N, 0.05, device=DEV)
+    xg, res = A.cg(_gpu(b), fixed_iter=20)
+    assert res.iters == 20 and res.status == 0
+    x = _cpu(xg)
+    assert _c_norm(x - xr.reshape(-1), pr.c) / _c_norm(xr, pr.c) <= 1e-9
+    assert (abs(res.rel_res - info["rel_res"]) <= 1e-6 * info["rel_res"]
+            or max(res.rel_res, info["rel_res"]) <= 1e-13)
+    assert _same_on_copies(pr, x)
+
+
 @pytest.mark.parametrize("mesh,N", [((5, 3, 2), 3), ((3, 3, 2), 7), ((3, 2, 3), 9), ((2, 3, 2), 11)])
 @MFMA
 def test_plain_cg_matches_oracle(mesh, N, mfma):
