@@ -115,6 +115,24 @@ def test_mixed_cg_all_orders(N):
     assert opcg.true_rel_residual(pr.ax, pr.shape4(b), pr.shape4(xv), pr.c) <= 1e-8 * (1 + 1e-3)
 
 
+@pytest.mark.parametrize("mesh", [(1, 2, 2), (2, 1, 1), (1, 1, 1)])
+def test_mixed_cg_linear_update_slab_meshes(mesh):
+    """FP32 inner-outer CG at N = 11, whose FP32 update is the linear tile,
+    on meshes one element across and on a single element."""
+    N = 11
+    pr = op.Problem(*mesh, N, 0.05)
+    b = workload.continuous_rhs(95, *mesh, N)
+    xr, _ = opcg.pcg(pr.ax, pr.shape4(b), pr.minv, pr.c, rtol=1e-12)
+    A = sem.SemOperator(*mesh, N, 0.05, lowprec="f32", device=DEV)
+    x, res = A.cg(torch.from_numpy(b).to(DEV), rtol=1e-8, mixed=True)
+    assert res.status == 0 and res.rel_res <= 1e-8
+    xv = x.cpu().numpy()
+    c = pr.c.reshape(-1)
+    err = math.sqrt(np.sum(c * (xv - xr.reshape(-1)) ** 2) / np.sum(c * xr.reshape(-1) ** 2))
+    assert err <= 1e-5
+    assert opcg.true_rel_residual(pr.ax, pr.shape4(b), pr.shape4(xv), pr.c) <= 1e-8 * (1 + 1e-3)
+
+
 def test_mixed_cg_repeatable_and_graph_stream():
     nx, ny, nz, N = 4, 4, 4, 7
     A = sem.SemOperator(nx, ny, nz, N, 0.05, lowprec="f32", device=DEV)
